@@ -1,0 +1,172 @@
+"""Seeded synthetic workloads for the CDG2 plaque operator.
+
+This module only draws random numbers and prepares input arrays: initial fields,
+coefficient sets and batched instance lists.  It contains none of the operator's
+arithmetic and is shared, as plain data, by the tests, the benchmark and the
+smoke check.
+
+Initial data (Section 2 asks for given initial fields n_i^0, c_i^0; Section 3.2
+takes U(0) as the L2 projection of U_0 onto V_h):
+
+    u_s(x) = 0.5 + sum_{j=1..4} a_sj * prod_{b periodic} cos(2 pi k_b x_b + phi_b)
+                                      * cos(pi k_w x_w)
+
+with integer wave numbers k in {0..3} (not all zero), phases phi ~ U[0, 2 pi),
+amplitudes a ~ U[0, 0.2] rescaled so that sum_j a_sj <= 0.4, hence
+u_s in [0.1, 0.9] (positive).  The wall factor cos(pi k_w x_w) has zero normal
+derivative on both walls.  Each term is a product of 1D factors, so its
+projection onto the tensor Legendre basis is the product of 1D projections,
+computed with numpy's Gauss-Legendre rule (p+3 points per direction).
+
+The paper gives the coefficients only as symbols, so a nondimensional base table
+is chosen here (fields stay in about [0.1, 0.9], chemotaxis is a small fraction
+of the diffusive flux, diffusion limits the explicit time step).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+COEFF_NAMES = [
+    "mu1", "mu2", "mu3", "nu1", "nu2", "nu3",
+    "chi0_11", "chi0_13", "chi0_21", "chi0_22",
+    "chith_11", "chith_13", "chith_21", "chith_22",
+    "d1", "d2", "gamma", "alpha1", "alpha2", "f1", "k",
+    "beta1", "beta2", "sigma", "c1_star", "c1_sstar",
+]
+
+BASE = dict(mu1=1e-2, mu2=5e-3, mu3=1e-3, nu1=5e-2, nu2=2e-2, nu3=2e-2,
+            chi0_11=2e-3, chi0_13=1e-3, chi0_21=1e-3, chi0_22=1e-3,
+            chith_11=0.5, chith_13=0.5, chith_21=0.5, chith_22=0.5,
+            d1=0.5, d2=0.2, gamma=-0.3, alpha1=1.0, alpha2=0.5, f1=0.4, k=0.8,
+            beta1=0.5, beta2=0.2, sigma=0.3, c1_star=0.45, c1_sstar=0.55)
+
+SEED_ROOT = 1403
+
+
+def base_coeffs() -> dict:
+    return dict(BASE)
+
+
+def rng_for(*key: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, *key])))
+
+
+def _basis_1d(p: int, xi: np.ndarray) -> np.ndarray:
+    """sqrt(2i+1) P_i(2 xi - 1) via numpy's Legendre evaluator, [len(xi), p+1]."""
+    t = 2.0 * xi - 1.0
+    out = np.empty((xi.size, p + 1))
+    for i in range(p + 1):
+        c = np.zeros(i + 1)
+        c[i] = 1.0
+        out[:, i] = math.sqrt(2 * i + 1) * np.polynomial.legendre.legval(t, c)
+    return out
+
+
+def _project_1d(fn, n: int, p: int) -> np.ndarray:
+    """1D L2-projection coefficients of fn on n cells of [0,1]: [n, p+1]."""
+    xg, wg = np.polynomial.legendre.leggauss(p + 3)
+    xi = 0.5 * (xg + 1.0)
+    w = 0.5 * wg
+    B = _basis_1d(p, xi)                                   # [Qg, p+1]
+    x = (np.arange(n)[:, None] + xi[None, :]) / n          # [n, Qg]
+    return np.einsum("q,nq,qm->nm", w, fn(x), B)
+
+
+def field_params(dim: int, wall_axis: int, key: tuple):
+    """Random Fourier description of the six initial fields."""
+    rng = rng_for(*key)
+    out = []
+    for _s in range(6):
+        terms = []
+        for _j in range(4):
+            while True:
+                k = rng.integers(0, 4, size=dim)
+                if k.any():
+                    break
+            phase = rng.uniform(0.0, 2.0 * math.pi, size=dim)
+            amp = rng.uniform(0.0, 0.2)
+            terms.append([k, phase, amp])
+        tot = sum(t[2] for t in terms)
+        if tot > 0.4:
+            for t in terms:
+                t[2] *= 0.4 / tot
+        out.append(terms)
+    return out
+
+
+def initial_modes(dim: int, n, p: int, key: tuple, wall_axis: int | None = None) -> np.ndarray:
+    """Modal coefficients U[6, E, (p+1)^dim] (float64) of the projected initial fields.
+    Element e = ix + nx (iy + ny iz); mode m = i + (p+1) (j + (p+1) k)."""
+    n = tuple(int(v) for v in n)[:dim]
+    wall = dim - 1 if wall_axis is None else wall_axis
+    q = p + 1
+    E = int(np.prod(n))
+    U = np.zeros((6, E, q ** dim))
+    U[:, :, 0] = 0.5
+    params = field_params(dim, wall, key)
+    for s in range(6):
+        acc = np.zeros((*reversed(n), *([q] * dim)))
+        for k, phase, amp in params[s]:
+            facs = []
+            for b in range(dim):
+                if b == wall:
+                    kb = int(k[b])
+                    fn = (lambda x, kb=kb: np.cos(math.pi * kb * x))
+                else:
+                    kb, ph = int(k[b]), float(phase[b])
+                    fn = (lambda x, kb=kb, ph=ph: np.cos(2.0 * math.pi * kb * x + ph))
+                facs.append(_project_1d(fn, n[b], p))          # [n_b, q]
+            if dim == 2:
+                term = np.einsum("ya,xb->yxab", facs[1], facs[0])
+            else:
+                term = np.einsum("zc,yb,xa->zyxcba", facs[2], facs[1], facs[0])
+            acc += amp * term
+        U[s] += acc.reshape(E, q ** dim)
+    return U
+
+
+def coeff_array(c: dict) -> np.ndarray:
+    return np.array([float(c[k]) for k in COEFF_NAMES])
+
+
+def sample_coeffs(key: tuple) -> dict:
+    """Each coefficient scaled by a log-uniform factor in [0.5, 1.5] (signs kept)."""
+    rng = rng_for(*key)
+    out = {}
+    for name in COEFF_NAMES:
+        out[name] = BASE[name] * math.exp(rng.uniform(math.log(0.5), math.log(1.5)))
+    return out
+
+
+def batch_instances(count: int = 256, key: tuple = (3,)):
+    """Batched workload: grid side N ~ U{32,48,64,96,128}, order p ~ U{1,2,3},
+    coefficients by sample_coeffs; instance i uses seed (1403, 3, i)."""
+    rng = rng_for(*key)
+    sides = [32, 48, 64, 96, 128]
+    out = []
+    for i in range(count):
+        N = int(sides[rng.integers(0, len(sides))])
+        p = int(rng.integers(1, 4))
+        out.append(dict(n=(N, N), order=p, coeffs=sample_coeffs((*key, i, 1)), key=(*key, i)))
+    return out
+
+
+def adjoint_coeffs() -> dict:
+    """Base table with the Heaviside thresholds moved outside the field range so that
+    the inflow switches stay fixed and the loss is differentiable."""
+    c = base_coeffs()
+    c["c1_star"] = 0.05
+    c["c1_sstar"] = 0.95
+    return c
+
+
+def adjoint_target_coeffs(key: tuple = (4,)) -> dict:
+    """Target coefficients: each of the 21 differentiable coefficients times
+    (1 + 0.1 xi_j) with xi_j = +-1 drawn from the seed."""
+    rng = rng_for(*key, 7)
+    c = adjoint_coeffs()
+    for name in COEFF_NAMES[:21]:
+        c[name] = c[name] * (1.0 + 0.1 * (1.0 if rng.integers(0, 2) else -1.0))
+    return c
