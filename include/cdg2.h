@@ -1,0 +1,145 @@
+/*
+ * cdg2.h -- C ABI of the MI355X (gfx950) CDG2 operator library for the
+ * six-species atherosclerotic-plaque model.
+ *
+ * Model (Section 2, eqs. (1)-(6) and their vector form): for
+ * U = (n1, n2, n3, c1, c2, c3),  dU/dt = -div(F(U) - A grad U) + S(U), with the
+ * chemotactic fluxes F_n1 = n1 w1, F_n2 = n2 w2, the tactic sensitivity
+ * chi(x, y, a, b) = a x / (y + b), constant diffusivities A = diag(mu, nu) and
+ * the reaction terms S; inflow boundary conditions of eqs. (7)-(9) on Gamma1
+ * (low end of the wall axis) and Gamma2 (high end).
+ *
+ * Discretisation (Section 3.1): discontinuous Galerkin on a uniform Cartesian
+ * grid of [0,1]^dim with the orthonormal tensor Legendre basis
+ * phi_i(xi) = sqrt(2i+1) P_i(2 xi - 1) per direction (so M = |K| I), p+1
+ * Gauss-Legendre points per direction, local Lax-Friedrichs convective flux,
+ * CDG2 diffusion flux 2 chi_e (A r_e([[U]]))|_{K^-_e} with lift factor
+ * chi_e = N/2 (2 for quads, 3 for hexes) and K^-_e the low-coordinate
+ * neighbour of each face.  Time (Section 3.2 replaced by an explicit method):
+ * f(U) = M^{-1} L_h(U), advanced by SSP-RK3 in Shu-Osher form.
+ *
+ * DOF layout (all state buffers): U[s][e][m], s = species in the order above,
+ * e = ix + nx (iy + ny iz), m = i + (p+1) (j + (p+1) k) (x mode fastest);
+ * cdg2_num_dofs() = 6 * E * (p+1)^dim elements of float64 (CDG2_FP64) or
+ * float32 (CDG2_FP32).
+ *
+ * Ownership: every state pointer is a DEVICE pointer to a caller-owned,
+ * contiguous buffer on the handle's device.  The library owns its tables, two
+ * stage buffers and small flag buffers; it copies the config at create.
+ *
+ * Asynchrony: calls that take device pointers enqueue work on the stream set by
+ * cdg2_set_stream (default: the null stream) and return; launch errors are
+ * returned at once, device-side conditions (non-finite values, a non-positive
+ * chemotaxis denominator) are returned by cdg2_sync.  Handles are not
+ * thread-safe.  No C++ exception crosses this boundary.
+ *
+ * Errors: 0 = CDG2_OK, negative values below; cdg2_last_error() returns a
+ * thread-local message for the last failing call.
+ */
+#ifndef CDG2_H
+#define CDG2_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CDG2_OK = 0,
+  CDG2_EINVAL = -1,     /* invalid argument or configuration */
+  CDG2_ENOMEM = -2,     /* device allocation failed */
+  CDG2_EHIP = -3,       /* HIP runtime error (message in cdg2_last_error) */
+  CDG2_ENONFINITE = -4, /* a NaN/Inf was written to a state buffer */
+  CDG2_EDOMAIN = -5     /* c + chi^th <= 0 met in a chemotactic sensitivity */
+};
+
+enum { CDG2_FP64 = 0, CDG2_FP32 = 1 };
+
+/* LLF dissipation rows: all six species (default) or only n1, n2. */
+enum { CDG2_LLF_ALL = 0, CDG2_LLF_CELLS = 1 };
+
+/* Coefficients of Section 2 (the paper gives symbols only).  The first 21 are
+ * the differentiable coefficients in this order: mu1..3, nu1..3 (motilities),
+ * chi0_{11,13,21,22}, chith_{11,13,21,22} (tactic sensitivities; 22 is the
+ * n2-by-n1 term of eq. (2)), d1, d2 (death rates), gamma (:= F < 0, constant),
+ * alpha1, alpha2 (neutralisation), f1 (production, constant), k (oxidation).
+ * The last five enter only the inflow conditions of eqs. (7)-(9): beta1,
+ * beta2, sigma, and the Heaviside thresholds c1*, c1**. */
+typedef struct {
+  double mu[3], nu[3];
+  double chi0[4], chith[4];
+  double d1, d2, gamma, alpha1, alpha2, f1, k;
+  double beta1, beta2, sigma, c1_star, c1_sstar;
+} cdg2_coeffs;
+
+#define CDG2_NCOEFF 26
+#define CDG2_NDIFF 21
+
+typedef struct {
+  int dim;              /* 2 or 3 */
+  int n[3];             /* cells per axis, each >= 2 (n[2] ignored for dim 2) */
+  int order;            /* p: 1..4 in 2D, 1..3 in 3D */
+  int precision;        /* CDG2_FP64 | CDG2_FP32 */
+  int wall_axis;        /* axis whose low end is Gamma1 and high end Gamma2
+                           (dim-1 normally); -1 = fully periodic */
+  int llf_mode;         /* CDG2_LLF_ALL | CDG2_LLF_CELLS */
+  double gamma1_in[2];  /* Gamma_{1,in} = [g0, g1] on the first tangential axis */
+  cdg2_coeffs coeffs;
+} cdg2_config;
+
+typedef struct cdg2_handle cdg2_handle;
+
+/* Create a handle for one grid / order / coefficient set (Sections 2, 3.1).
+ * Validates cfg (CDG2_EINVAL), builds the 1D tables on the host and allocates
+ * the stage buffers on the current device (CDG2_ENOMEM).  No kernel launch. */
+int cdg2_create(const cdg2_config* cfg, cdg2_handle** out);
+
+/* Release everything the handle owns; NULL is accepted. */
+int cdg2_destroy(cdg2_handle* h);
+
+/* Stream for all later calls (a hipStream_t, e.g. torch's current stream). */
+int cdg2_set_stream(cdg2_handle* h, void* hip_stream);
+
+/* Replace the coefficient set (same grid and order). */
+int cdg2_set_coeffs(cdg2_handle* h, const cdg2_coeffs* c);
+
+/* Number of state entries, 6 * E * (p+1)^dim. */
+size_t cdg2_num_dofs(const cdg2_handle* h);
+
+/* dUdt = M^{-1} L_h(U) (Section 3.2: the ODE right-hand side, not the
+ * pre-mass residual).  U and dUdt: device buffers of cdg2_num_dofs entries;
+ * they must not overlap (CDG2_EINVAL). */
+int cdg2_apply_operator(cdg2_handle* h, const void* U, void* dUdt);
+
+/* nsteps SSP-RK3 steps of size dt, in place on U:
+ *   U1 = U + dt f(U);  U2 = 3/4 U + 1/4 (U1 + dt f(U1));
+ *   U <- 1/3 U + 2/3 (U2 + dt f(U2)).
+ * Each stage is one fused launch (operator + stage combination); the two
+ * intermediate states live in the handle's stage buffers. */
+int cdg2_rk_step(cdg2_handle* h, void* U, double dt, int nsteps);
+
+/* CFL time step for state U (synchronous: returns after the device work):
+ *   dt = cfl / (rho_hat a_max sum_a h_a^-2 / 2.51 + (2p+1) lam_max sum_a h_a^-1
+ *               + r_max / 2.51),
+ * with rho_hat the spectral radius of the 1D diffusion operator (a = h = 1),
+ * lam_max the largest chemotactic velocity component and
+ * r_max = d1 + d2 + |gamma| + k + alpha1 max n1 + alpha2 max n2, both over the
+ * volume quadrature points. */
+int cdg2_max_dt(cdg2_handle* h, const void* U, double cfl, double* dt);
+
+/* Wait for the handle's stream and report device-side conditions raised since
+ * the last cdg2_sync (CDG2_ENONFINITE, CDG2_EDOMAIN); clears them. */
+int cdg2_sync(cdg2_handle* h);
+
+/* Spectral constant rho_hat used by cdg2_max_dt (host-computed at create). */
+double cdg2_rho_hat(const cdg2_handle* h);
+
+/* Thread-local message of the last error. */
+const char* cdg2_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CDG2_H */

@@ -336,7 +336,12 @@ class Oracle:
         # n^- = +e_ax: normal components
         dnm = gm[..., ax]
         dnp = gp[..., ax]
-        jump = um - up                                               # u^- - u^+
+        # jump u^- - u^+, formed basis function by basis function: the constant mode
+        # (phi_0 = 1 on both sides) cancels exactly, so the O(1) cell means do not
+        # leave their rounding in the small jump (same value in exact arithmetic).
+        jump = (Um[..., 0] - Up[..., 0]).unsqueeze(-1) \
+            + torch.einsum("s...m,tm->s...t", Um[..., 1:], F["PhiHi"][:, 1:]) \
+            - torch.einsum("s...m,tm->s...t", Up[..., 1:], F["PhiLo"][:, 1:])
         # LLF (Section 3.1): F^ n = 1/2 (F^- + F^+).n + 1/2 lam (u^- - u^+)
         w1m, w2m = self.velocities(um, gm, th)
         w1p, w2p = self.velocities(up, gp, th)
@@ -459,13 +464,14 @@ class Oracle:
         return U
 
     # -- CFL time step ----------------------------------------------------------
-    def spectral_constant(self) -> float:
+    def spectral_constant(self, ncell: int = 4) -> float:
         """rho_hat: spectral radius of M^{-1} K for the pure diffusion operator
-        (a = 1) on a fully periodic 8^d grid, times h^2 / d.  Computed matrix-free
-        with a library Lanczos eigen-solver (scipy eigsh) on the oracle operator."""
+        (a = 1) on a fully periodic ncell^d grid, times h^2 / d.  Computed
+        matrix-free with a library Lanczos eigen-solver (scipy eigsh) on the
+        oracle operator."""
         import numpy as np
         from scipy.sparse.linalg import LinearOperator, eigsh
-        cfg = Config(dim=self.d, n=(8,) * self.d, order=self.p, wall_axis=-1,
+        cfg = Config(dim=self.d, n=(ncell,) * self.d, order=self.p, wall_axis=-1,
                      coeffs=diffusion_only_coeffs(1.0))
         o = Oracle(cfg)
         shp = (NSPEC, o.E, o.nm)
@@ -476,9 +482,9 @@ class Oracle:
             return (-o.apply(X)).reshape(-1).numpy()
 
         op = LinearOperator((n, n), matvec=mv, dtype=np.float64)
-        ev = eigsh(op, k=1, which="LA", tol=1e-10, return_eigenvectors=False,
+        ev = eigsh(op, k=1, which="LA", tol=0, return_eigenvectors=False,
                    v0=np.random.default_rng(0).standard_normal(n))
-        return float(ev[0]) * (1.0 / 8) ** 2 / self.d
+        return float(ev[0]) * (1.0 / ncell) ** 2 / self.d
 
     def max_dt(self, U, cfl=0.9, rho_hat=None):
         """dt = cfl / (rho_hat a_max sum_a h_a^-2 / 2.51 + (2p+1) lam_max sum_a h_a^-1

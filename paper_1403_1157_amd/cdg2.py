@@ -1,0 +1,232 @@
+"""ctypes binding of libcdg2.so (C ABI in include/cdg2.h).
+
+Argument marshalling only: every step of the operator runs in the HIP library.
+torch tensors are used for device memory and streams.  The functions keep the
+C names (cdg2_create, cdg2_apply_operator, ...); :class:`Operator` wraps a handle.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcdg2.so")
+
+CDG2_OK, CDG2_EINVAL, CDG2_ENOMEM, CDG2_EHIP, CDG2_ENONFINITE, CDG2_EDOMAIN = 0, -1, -2, -3, -4, -5
+CDG2_FP64, CDG2_FP32 = 0, 1
+CDG2_LLF_ALL, CDG2_LLF_CELLS = 0, 1
+
+COEFF_NAMES = [
+    "mu1", "mu2", "mu3", "nu1", "nu2", "nu3",
+    "chi0_11", "chi0_13", "chi0_21", "chi0_22",
+    "chith_11", "chith_13", "chith_21", "chith_22",
+    "d1", "d2", "gamma", "alpha1", "alpha2", "f1", "k",
+    "beta1", "beta2", "sigma", "c1_star", "c1_sstar",
+]
+
+_d = ctypes.c_double
+
+
+class cdg2_coeffs(ctypes.Structure):
+    _fields_ = [("mu", _d * 3), ("nu", _d * 3), ("chi0", _d * 4), ("chith", _d * 4),
+                ("d1", _d), ("d2", _d), ("gamma", _d), ("alpha1", _d), ("alpha2", _d),
+                ("f1", _d), ("k", _d), ("beta1", _d), ("beta2", _d), ("sigma", _d),
+                ("c1_star", _d), ("c1_sstar", _d)]
+
+
+class cdg2_config(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("order", ctypes.c_int),
+                ("precision", ctypes.c_int), ("wall_axis", ctypes.c_int),
+                ("llf_mode", ctypes.c_int), ("gamma1_in", _d * 2), ("coeffs", cdg2_coeffs)]
+
+
+class CDG2Error(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"cdg2 error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libcdg2.so; raise if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1403_1157_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    L.cdg2_create.argtypes = [ctypes.POINTER(cdg2_config), ctypes.POINTER(P)]
+    L.cdg2_destroy.argtypes = [P]
+    L.cdg2_set_stream.argtypes = [P, P]
+    L.cdg2_set_coeffs.argtypes = [P, ctypes.POINTER(cdg2_coeffs)]
+    L.cdg2_num_dofs.argtypes = [P]
+    L.cdg2_num_dofs.restype = ctypes.c_size_t
+    L.cdg2_apply_operator.argtypes = [P, P, P]
+    L.cdg2_rk_step.argtypes = [P, P, _d, ctypes.c_int]
+    L.cdg2_max_dt.argtypes = [P, P, _d, ctypes.POINTER(_d)]
+    L.cdg2_sync.argtypes = [P]
+    L.cdg2_rho_hat.argtypes = [P]
+    L.cdg2_rho_hat.restype = _d
+    L.cdg2_last_error.argtypes = []
+    L.cdg2_last_error.restype = ctypes.c_char_p
+    for name in ("cdg2_create", "cdg2_destroy", "cdg2_set_stream", "cdg2_set_coeffs",
+                 "cdg2_apply_operator", "cdg2_rk_step", "cdg2_max_dt", "cdg2_sync"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != CDG2_OK:
+        raise CDG2Error(rc, lib().cdg2_last_error().decode())
+
+
+def make_coeffs(c: dict) -> cdg2_coeffs:
+    v = [float(c[k]) for k in COEFF_NAMES]
+    s = cdg2_coeffs()
+    s.mu[:] = v[0:3]
+    s.nu[:] = v[3:6]
+    s.chi0[:] = v[6:10]
+    s.chith[:] = v[10:14]
+    (s.d1, s.d2, s.gamma, s.alpha1, s.alpha2, s.f1, s.k,
+     s.beta1, s.beta2, s.sigma, s.c1_star, s.c1_sstar) = v[14:26]
+    return s
+
+
+def make_config(dim: int, n, order: int, coeffs: dict, precision: str = "fp64",
+                wall_axis: int | None = None, llf_mode: str = "all",
+                gamma1_in=(0.0, 1.0)) -> cdg2_config:
+    cfg = cdg2_config()
+    cfg.dim = int(dim)
+    nn = list(n) + [1] * (3 - len(n))
+    cfg.n[:] = [int(v) for v in nn[:3]]
+    cfg.order = int(order)
+    cfg.precision = CDG2_FP32 if precision == "fp32" else CDG2_FP64
+    cfg.wall_axis = dim - 1 if wall_axis is None else int(wall_axis)
+    cfg.llf_mode = CDG2_LLF_CELLS if llf_mode == "cells" else CDG2_LLF_ALL
+    cfg.gamma1_in[:] = [float(gamma1_in[0]), float(gamma1_in[1])]
+    cfg.coeffs = make_coeffs(coeffs)
+    return cfg
+
+
+# ---- C-named entry points ----------------------------------------------------
+
+def cdg2_create(cfg: cdg2_config) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().cdg2_create(ctypes.byref(cfg), ctypes.byref(h)))
+    return h
+
+
+def cdg2_destroy(h) -> None:
+    _check(lib().cdg2_destroy(h))
+
+
+def cdg2_set_stream(h, stream: int) -> None:
+    _check(lib().cdg2_set_stream(h, ctypes.c_void_p(stream)))
+
+
+def cdg2_set_coeffs(h, c: dict) -> None:
+    s = make_coeffs(c)
+    _check(lib().cdg2_set_coeffs(h, ctypes.byref(s)))
+
+
+def cdg2_num_dofs(h) -> int:
+    return int(lib().cdg2_num_dofs(h))
+
+
+def cdg2_apply_operator(h, U_ptr: int, out_ptr: int) -> None:
+    _check(lib().cdg2_apply_operator(h, ctypes.c_void_p(U_ptr), ctypes.c_void_p(out_ptr)))
+
+
+def cdg2_rk_step(h, U_ptr: int, dt: float, nsteps: int) -> None:
+    _check(lib().cdg2_rk_step(h, ctypes.c_void_p(U_ptr), float(dt), int(nsteps)))
+
+
+def cdg2_max_dt(h, U_ptr: int, cfl: float) -> float:
+    dt = _d()
+    _check(lib().cdg2_max_dt(h, ctypes.c_void_p(U_ptr), float(cfl), ctypes.byref(dt)))
+    return dt.value
+
+
+def cdg2_sync(h) -> None:
+    _check(lib().cdg2_sync(h))
+
+
+def cdg2_rho_hat(h) -> float:
+    return float(lib().cdg2_rho_hat(h))
+
+
+# ---- convenience wrapper -------------------------------------------------------
+
+class Operator:
+    """One grid / order / coefficient set; tensors are torch CUDA tensors of shape
+    (6, E, (p+1)^dim) in float64 (or float32 with precision="fp32")."""
+
+    def __init__(self, dim, n, order, coeffs, precision="fp64", wall_axis=None,
+                 llf_mode="all", gamma1_in=(0.0, 1.0)):
+        self.dim, self.order = int(dim), int(order)
+        self.n = tuple(int(v) for v in n)[:dim]
+        self.dtype = torch.float32 if precision == "fp32" else torch.float64
+        self.cfg = make_config(dim, n, order, coeffs, precision, wall_axis, llf_mode, gamma1_in)
+        self.h = cdg2_create(self.cfg)
+        self.E = 1
+        for v in self.n:
+            self.E *= v
+        self.nm = (order + 1) ** dim
+        self.shape = (6, self.E, self.nm)
+        assert cdg2_num_dofs(self.h) == 6 * self.E * self.nm
+
+    def _arg(self, t: torch.Tensor) -> int:
+        if not (t.is_cuda and t.dtype == self.dtype and t.is_contiguous() and t.numel() == 6 * self.E * self.nm):
+            raise ValueError(f"expected a contiguous CUDA {self.dtype} tensor of {self.shape}")
+        return t.data_ptr()
+
+    def _stream(self):
+        cdg2_set_stream(self.h, torch.cuda.current_stream().cuda_stream)
+
+    def apply(self, U: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty_like(U)
+        self._stream()
+        cdg2_apply_operator(self.h, self._arg(U), self._arg(out))
+        return out
+
+    def rk_step(self, U: torch.Tensor, dt: float, nsteps: int = 1) -> torch.Tensor:
+        self._stream()
+        cdg2_rk_step(self.h, self._arg(U), dt, nsteps)
+        return U
+
+    def max_dt(self, U: torch.Tensor, cfl: float = 0.9) -> float:
+        self._stream()
+        return cdg2_max_dt(self.h, self._arg(U), cfl)
+
+    def set_coeffs(self, coeffs: dict) -> None:
+        cdg2_set_coeffs(self.h, coeffs)
+
+    def sync(self) -> None:
+        self._stream()
+        cdg2_sync(self.h)
+
+    @property
+    def rho_hat(self) -> float:
+        return cdg2_rho_hat(self.h)
+
+    def close(self):
+        if self.h is not None:
+            cdg2_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cdg2_last_error() -> str:
+    return lib().cdg2_last_error().decode()

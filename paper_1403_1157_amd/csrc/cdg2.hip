@@ -1,0 +1,311 @@
+// C-ABI implementation of libcdg2 (declarations and contract in include/cdg2.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/cdg2.h"
+#include "cfl_kernel.hpp"
+#include "op_kernel.hpp"
+#include "tables.cpp"
+
+using namespace cdg2;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t _e = (expr);                                                           \
+    if (_e != hipSuccess) return fail(CDG2_EHIP, "%s: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+}  // namespace
+
+struct cdg2_handle {
+  cdg2_config cfg;
+  Tables tb;
+  Geo geo;
+  Coef coef;
+  int dim, p, fp32;
+  size_t ndof;
+  void* stage[2] = {nullptr, nullptr};
+  int* flags = nullptr;
+  unsigned long long* red = nullptr;
+  hipStream_t stream = nullptr;
+  double rho_hat = 0.0;
+};
+
+namespace {
+
+void coef_from(const cdg2_coeffs& c, Coef* o) {
+  const double v[K_NCOEFF] = {c.mu[0], c.mu[1], c.mu[2], c.nu[0], c.nu[1], c.nu[2],
+                              c.chi0[0], c.chi0[1], c.chi0[2], c.chi0[3],
+                              c.chith[0], c.chith[1], c.chith[2], c.chith[3],
+                              c.d1, c.d2, c.gamma, c.alpha1, c.alpha2, c.f1, c.k,
+                              c.beta1, c.beta2, c.sigma, c.c1_star, c.c1_sstar};
+  std::memcpy(o->c, v, sizeof v);
+}
+
+int validate(const cdg2_config* c) {
+  if (!c) return fail(CDG2_EINVAL, "config is NULL");
+  if (c->dim != 2 && c->dim != 3) return fail(CDG2_EINVAL, "dim must be 2 or 3 (got %d)", c->dim);
+  int pmax = c->dim == 2 ? 4 : 3;
+  if (c->order < 1 || c->order > pmax)
+    return fail(CDG2_EINVAL, "order must be in 1..%d for dim %d (got %d)", pmax, c->dim, c->order);
+  for (int a = 0; a < c->dim; ++a)
+    if (c->n[a] < 2 || c->n[a] > (1 << 16)) return fail(CDG2_EINVAL, "n[%d] must be in 2..65536", a);
+  if (c->precision != CDG2_FP64 && c->precision != CDG2_FP32)
+    return fail(CDG2_EINVAL, "precision must be CDG2_FP64 or CDG2_FP32");
+  if (c->wall_axis < -1 || c->wall_axis >= c->dim) return fail(CDG2_EINVAL, "wall_axis out of range");
+  if (c->llf_mode != CDG2_LLF_ALL && c->llf_mode != CDG2_LLF_CELLS) return fail(CDG2_EINVAL, "bad llf_mode");
+  if (!(c->gamma1_in[0] <= c->gamma1_in[1])) return fail(CDG2_EINVAL, "gamma1_in must be an interval");
+  const double* v = &c->coeffs.mu[0];
+  for (int i = 0; i < CDG2_NCOEFF; ++i)
+    if (!std::isfinite(v[i])) return fail(CDG2_EINVAL, "coefficient %d is not finite", i);
+  for (int i = 0; i < 6; ++i)
+    if (v[i] < 0) return fail(CDG2_EINVAL, "diffusivities must be >= 0");
+  size_t E = (size_t)c->n[0] * c->n[1] * (c->dim == 3 ? c->n[2] : 1);
+  size_t nm = 1;
+  for (int a = 0; a < c->dim; ++a) nm *= (size_t)(c->order + 1);
+  if (6 * E * nm > (size_t)1 << 34) return fail(CDG2_EINVAL, "problem too large");
+  return CDG2_OK;
+}
+
+void build_geo(const cdg2_config& c, Geo* g) {
+  std::memset(g, 0, sizeof(Geo));
+  g->E = 1;
+  for (int a = 0; a < 3; ++a) {
+    g->n[a] = a < c.dim ? c.n[a] : 1;
+    g->h[a] = 1.0 / g->n[a];
+    g->ih[a] = (double)g->n[a];
+    g->E *= g->n[a];
+  }
+  g->wall = c.wall_axis;
+  g->llf_cells = c.llf_mode == CDG2_LLF_CELLS;
+  g->vol = 1.0;
+  for (int a = 0; a < c.dim; ++a) g->vol *= g->h[a];
+  for (int a = 0; a < c.dim; ++a) g->area[a] = g->vol / g->h[a];
+  g->g1in[0] = c.gamma1_in[0];
+  g->g1in[1] = c.gamma1_in[1];
+  g->chi_e = 0.5 * (2 * c.dim);  // N/2, N = 2d faces per cell
+}
+
+// ---- launch dispatch ----------------------------------------------------------
+
+template <int D, int P>
+struct LaunchCfg {
+  // cells per workgroup and workgroup size
+  static constexpr int EPW = D == 3 ? 1 : (P <= 2 ? 4 : 2);
+  static constexpr int NT = D == 3 ? 64 : 128;
+};
+
+template <int D, int P, typename T>
+hipError_t launch_op(cdg2_handle* h, const void* U, const void* U0, void* out, double dt, double ca,
+                     double cb, int stage) {
+  using L = LaunchCfg<D, P>;
+  int nb = (h->geo.E + L::EPW - 1) / L::EPW;
+  hipLaunchKernelGGL((op_kernel<D, P, T, L::EPW, L::NT>), dim3(nb), dim3(L::NT), 0, h->stream, h->tb,
+                     h->geo, h->coef, (const T*)U, (const T*)U0, (T*)out, (T)dt, (T)ca, (T)cb, stage,
+                     h->flags);
+  return hipGetLastError();
+}
+
+template <int D, int P, typename T>
+hipError_t launch_cfl(cdg2_handle* h, const void* U) {
+  using L = LaunchCfg<D, P>;
+  int nb = (h->geo.E + L::EPW - 1) / L::EPW;
+  hipLaunchKernelGGL((cfl_kernel<D, P, T, L::EPW, L::NT>), dim3(nb), dim3(L::NT), 0, h->stream, h->tb,
+                     h->geo, h->coef, (const T*)U, h->red, h->flags);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_op(cdg2_handle* h, const void* U, const void* U0, void* out, double dt, double ca,
+                       double cb, int stage) {
+  switch (h->dim * 10 + h->p) {
+    case 21: return launch_op<2, 1, T>(h, U, U0, out, dt, ca, cb, stage);
+    case 22: return launch_op<2, 2, T>(h, U, U0, out, dt, ca, cb, stage);
+    case 23: return launch_op<2, 3, T>(h, U, U0, out, dt, ca, cb, stage);
+    case 24: return launch_op<2, 4, T>(h, U, U0, out, dt, ca, cb, stage);
+    case 31: return launch_op<3, 1, T>(h, U, U0, out, dt, ca, cb, stage);
+    case 32: return launch_op<3, 2, T>(h, U, U0, out, dt, ca, cb, stage);
+    case 33: return launch_op<3, 3, T>(h, U, U0, out, dt, ca, cb, stage);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t dispatch_cfl(cdg2_handle* h, const void* U) {
+  switch (h->dim * 10 + h->p) {
+    case 21: return launch_cfl<2, 1, T>(h, U);
+    case 22: return launch_cfl<2, 2, T>(h, U);
+    case 23: return launch_cfl<2, 3, T>(h, U);
+    case 24: return launch_cfl<2, 4, T>(h, U);
+    case 31: return launch_cfl<3, 1, T>(h, U);
+    case 32: return launch_cfl<3, 2, T>(h, U);
+    case 33: return launch_cfl<3, 3, T>(h, U);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t run_op(cdg2_handle* h, const void* U, const void* U0, void* out, double dt, double ca, double cb,
+                  int stage) {
+  return h->fp32 ? dispatch_op<float>(h, U, U0, out, dt, ca, cb, stage)
+                 : dispatch_op<double>(h, U, U0, out, dt, ca, cb, stage);
+}
+
+bool overlap(const void* a, const void* b, size_t bytes) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + bytes && y < x + bytes;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cdg2_create(const cdg2_config* cfg, cdg2_handle** out) {
+  if (!out) return fail(CDG2_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  cdg2_handle* h = new (std::nothrow) cdg2_handle();
+  if (!h) return fail(CDG2_ENOMEM, "host allocation failed");
+  h->cfg = *cfg;
+  h->dim = cfg->dim;
+  h->p = cfg->order;
+  h->fp32 = cfg->precision == CDG2_FP32;
+  build_tables(h->p, &h->tb);
+  build_geo(*cfg, &h->geo);
+  coef_from(cfg->coeffs, &h->coef);
+  size_t nm = 1;
+  for (int a = 0; a < h->dim; ++a) nm *= (size_t)(h->p + 1);
+  h->ndof = 6 * (size_t)h->geo.E * nm;
+  h->rho_hat = spectral_constant_1d(h->p, h->geo.chi_e);
+  size_t bytes = h->ndof * (h->fp32 ? 4 : 8);
+  for (int k = 0; k < 2; ++k) {
+    if (hipMalloc(&h->stage[k], bytes) != hipSuccess) {
+      cdg2_destroy(h);
+      return fail(CDG2_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+    }
+  }
+  if (hipMalloc((void**)&h->flags, 64) != hipSuccess || hipMalloc((void**)&h->red, 64) != hipSuccess) {
+    cdg2_destroy(h);
+    return fail(CDG2_ENOMEM, "hipMalloc of flag buffers failed");
+  }
+  if (hipMemset(h->flags, 0, 64) != hipSuccess) {
+    cdg2_destroy(h);
+    return fail(CDG2_EHIP, "hipMemset failed");
+  }
+  *out = h;
+  return CDG2_OK;
+}
+
+int cdg2_destroy(cdg2_handle* h) {
+  if (!h) return CDG2_OK;
+  for (int k = 0; k < 2; ++k)
+    if (h->stage[k]) (void)hipFree(h->stage[k]);
+  if (h->flags) (void)hipFree(h->flags);
+  if (h->red) (void)hipFree(h->red);
+  delete h;
+  return CDG2_OK;
+}
+
+int cdg2_set_stream(cdg2_handle* h, void* s) {
+  if (!h) return fail(CDG2_EINVAL, "handle is NULL");
+  h->stream = (hipStream_t)s;
+  return CDG2_OK;
+}
+
+int cdg2_set_coeffs(cdg2_handle* h, const cdg2_coeffs* c) {
+  if (!h || !c) return fail(CDG2_EINVAL, "NULL argument");
+  cdg2_config tmp = h->cfg;
+  tmp.coeffs = *c;
+  int rc = validate(&tmp);
+  if (rc) return rc;
+  h->cfg.coeffs = *c;
+  coef_from(*c, &h->coef);
+  return CDG2_OK;
+}
+
+size_t cdg2_num_dofs(const cdg2_handle* h) { return h ? h->ndof : 0; }
+
+double cdg2_rho_hat(const cdg2_handle* h) { return h ? h->rho_hat : 0.0; }
+
+int cdg2_apply_operator(cdg2_handle* h, const void* U, void* dUdt) {
+  if (!h || !U || !dUdt) return fail(CDG2_EINVAL, "NULL argument");
+  size_t bytes = h->ndof * (h->fp32 ? 4 : 8);
+  if (overlap(U, dUdt, bytes)) return fail(CDG2_EINVAL, "U and dUdt overlap");
+  HIP_TRY(run_op(h, U, nullptr, dUdt, 0.0, 0.0, 1.0, 0));
+  return CDG2_OK;
+}
+
+int cdg2_rk_step(cdg2_handle* h, void* U, double dt, int nsteps) {
+  if (!h || !U) return fail(CDG2_EINVAL, "NULL argument");
+  if (nsteps < 0) return fail(CDG2_EINVAL, "nsteps < 0");
+  if (!std::isfinite(dt)) return fail(CDG2_EINVAL, "dt is not finite");
+  size_t bytes = h->ndof * (h->fp32 ? 4 : 8);
+  if (overlap(U, h->stage[0], bytes) || overlap(U, h->stage[1], bytes))
+    return fail(CDG2_EINVAL, "U overlaps a stage buffer");
+  for (int n = 0; n < nsteps; ++n) {
+    HIP_TRY(run_op(h, U, nullptr, h->stage[0], dt, 0.0, 1.0, 1));
+    HIP_TRY(run_op(h, h->stage[0], U, h->stage[1], dt, 0.75, 0.25, 2));
+    HIP_TRY(run_op(h, h->stage[1], U, U, dt, 1.0 / 3.0, 2.0 / 3.0, 3));
+  }
+  return CDG2_OK;
+}
+
+int cdg2_max_dt(cdg2_handle* h, const void* U, double cfl, double* dt) {
+  if (!h || !U || !dt) return fail(CDG2_EINVAL, "NULL argument");
+  if (!(cfl > 0)) return fail(CDG2_EINVAL, "cfl must be > 0");
+  HIP_TRY(hipMemsetAsync(h->red, 0, 3 * sizeof(unsigned long long), h->stream));
+  HIP_TRY(h->fp32 ? dispatch_cfl<float>(h, U) : dispatch_cfl<double>(h, U));
+  unsigned long long r[3];
+  HIP_TRY(hipMemcpyAsync(r, h->red, sizeof r, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  double v[3];
+  std::memcpy(v, r, sizeof v);
+  const double* c = h->coef.c;
+  double amax = 0.0;
+  for (int s = 0; s < 6; ++s) amax = std::fmax(amax, std::fabs(c[s]));
+  double sih2 = 0.0, sih = 0.0;
+  for (int a = 0; a < h->dim; ++a) {
+    sih2 += h->geo.ih[a] * h->geo.ih[a];
+    sih += h->geo.ih[a];
+  }
+  double rmax = c[K_D1] + c[K_D2] + std::fabs(c[K_GAM]) + c[K_K] + c[K_AL1] * v[1] + c[K_AL2] * v[2];
+  double inv = h->rho_hat * amax * sih2 / 2.51 + (2 * h->p + 1) * v[0] * sih + rmax / 2.51;
+  *dt = inv > 0 ? cfl / inv : INFINITY;
+  return CDG2_OK;
+}
+
+int cdg2_sync(cdg2_handle* h) {
+  if (!h) return fail(CDG2_EINVAL, "handle is NULL");
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  int f = 0;
+  HIP_TRY(hipMemcpy(&f, h->flags, sizeof f, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemset(h->flags, 0, sizeof(int)));
+  if (f & FLAG_NONFINITE) return fail(CDG2_ENONFINITE, "non-finite value written to a state buffer");
+  if (f & FLAG_DOMAIN) return fail(CDG2_EDOMAIN, "c + chi^th <= 0 in a chemotactic sensitivity");
+  return CDG2_OK;
+}
+
+const char* cdg2_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function declared in include/cdg2.h, and rejects invalid configurations before
+touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1403_1157_amd import cdg2 as B
+from paper_1403_1157_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(cdg2_\w+)\s*\(", src))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    names = declared_functions()
+    assert "cdg2_apply_operator" in names and "cdg2_rk_step" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_binding_exposes_the_c_names():
+    for n in declared_functions():
+        assert hasattr(B, n), n
+
+
+def test_struct_layout_matches_header():
+    # 26 doubles of coefficients; config = 6 ints + pad to 8 + 2 doubles + coeffs
+    assert ctypes.sizeof(B.cdg2_coeffs) == 26 * 8
+    assert B.cdg2_config.coeffs.offset == ctypes.sizeof(ctypes.c_int) * 8 + 16
+
+
+@pytest.mark.parametrize("field,value", [
+    ("dim", 4), ("dim", 1), ("order", 0), ("order", 5), ("n0", 1), ("wall_axis", 3),
+    ("wall_axis", -2), ("precision", 7), ("llf_mode", 3), ("g1", (0.8, 0.2)),
+    ("nan", None), ("neg_diff", None), ("order3d", 4)])
+def test_invalid_config_rejected(field, value):
+    c = inputs.base_coeffs()
+    dim, order = 2, 2
+    if field == "order3d":
+        dim, order = 3, 4
+    cfg = B.make_config(dim, (8, 8, 8), order, c)
+    if field == "dim":
+        cfg.dim = value
+    elif field == "order":
+        cfg.order = value
+    elif field == "n0":
+        cfg.n[0] = value
+    elif field == "wall_axis":
+        cfg.wall_axis = value
+    elif field == "precision":
+        cfg.precision = value
+    elif field == "llf_mode":
+        cfg.llf_mode = value
+    elif field == "g1":
+        cfg.gamma1_in[:] = list(value)
+    elif field == "nan":
+        cfg.coeffs.k = float("nan")
+    elif field == "neg_diff":
+        cfg.coeffs.mu[1] = -1.0
+    with pytest.raises(B.CDG2Error) as ei:
+        B.cdg2_create(cfg)
+    assert ei.value.code == B.CDG2_EINVAL
+    assert len(B.lib().cdg2_last_error()) > 0
+
+
+def test_null_arguments_rejected():
+    L = B.lib()
+    assert L.cdg2_create(None, None) == B.CDG2_EINVAL
+    assert L.cdg2_apply_operator(None, None, None) == B.CDG2_EINVAL
+    assert L.cdg2_rk_step(None, None, 0.1, 1) == B.CDG2_EINVAL
+    assert L.cdg2_destroy(None) == B.CDG2_OK
+    assert L.cdg2_num_dofs(None) == 0

@@ -191,6 +191,9 @@ def _uniform(o, vals):
 def test_uniform_state_linear_reactions_exact_solution():
     c = inputs.base_coeffs()
     c.update(alpha1=0.0, alpha2=0.0, c1_star=5.0, c1_sstar=5.0, sigma=0.0)
+    # small diffusivities keep the large reaction time step inside the SSP-RK3
+    # stability region for the (zero) higher modes
+    c.update(mu1=1e-4, mu2=1e-4, mu3=1e-4, nu1=1e-4, nu2=1e-4, nu3=1e-4)
     o = Oracle(Config(dim=2, n=(3, 3), order=1, coeffs=c))
     v0 = [0.4, 0.5, 0.3, 0.6, 0.45, 0.35]
     d1, d2, gm, f1, k = c["d1"], c["d2"], c["gamma"], c["f1"], c["k"]
