@@ -42,6 +42,7 @@ struct cdg2_handle {
   Tables tb;
   Geo geo;
   Coef coef;
+  Params* dprm = nullptr;   // device copy of tb, geo, coef
   int dim, p, fp32;
   size_t ndof;
   void* stage[2] = {nullptr, nullptr};
@@ -120,9 +121,8 @@ hipError_t launch_op(cdg2_handle* h, const void* U, const void* U0, void* out, d
                      double cb, int stage) {
   using L = LaunchCfg<D, P>;
   int nb = (h->geo.E + L::EPW - 1) / L::EPW;
-  hipLaunchKernelGGL((op_kernel<D, P, T, L::EPW, L::NT>), dim3(nb), dim3(L::NT), 0, h->stream, h->tb,
-                     h->geo, h->coef, (const T*)U, (const T*)U0, (T*)out, (T)dt, (T)ca, (T)cb, stage,
-                     h->flags);
+  hipLaunchKernelGGL((op_kernel<D, P, T, L::EPW, L::NT>), dim3(nb), dim3(L::NT), 0, h->stream, h->dprm,
+                     (const T*)U, (const T*)U0, (T*)out, (T)dt, (T)ca, (T)cb, stage, h->flags);
   return hipGetLastError();
 }
 
@@ -130,8 +130,8 @@ template <int D, int P, typename T>
 hipError_t launch_cfl(cdg2_handle* h, const void* U) {
   using L = LaunchCfg<D, P>;
   int nb = (h->geo.E + L::EPW - 1) / L::EPW;
-  hipLaunchKernelGGL((cfl_kernel<D, P, T, L::EPW, L::NT>), dim3(nb), dim3(L::NT), 0, h->stream, h->tb,
-                     h->geo, h->coef, (const T*)U, h->red, h->flags);
+  hipLaunchKernelGGL((cfl_kernel<D, P, T, L::EPW, L::NT>), dim3(nb), dim3(L::NT), 0, h->stream, h->dprm,
+                     (const T*)U, h->red, h->flags);
   return hipGetLastError();
 }
 
@@ -170,6 +170,15 @@ hipError_t run_op(cdg2_handle* h, const void* U, const void* U0, void* out, doub
                  : dispatch_op<double>(h, U, U0, out, dt, ca, cb, stage);
 }
 
+hipError_t upload_params(cdg2_handle* h) {
+  Params p;
+  p.tb = h->tb;
+  p.g = h->geo;
+  p.cf = h->coef;
+  // pageable source: the copy is staged before the call returns, in stream order
+  return hipMemcpyAsync(h->dprm, &p, sizeof(Params), hipMemcpyHostToDevice, h->stream);
+}
+
 bool overlap(const void* a, const void* b, size_t bytes) {
   const char* x = (const char*)a;
   const char* y = (const char*)b;
@@ -205,13 +214,15 @@ int cdg2_create(const cdg2_config* cfg, cdg2_handle** out) {
       return fail(CDG2_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
     }
   }
-  if (hipMalloc((void**)&h->flags, 64) != hipSuccess || hipMalloc((void**)&h->red, 64) != hipSuccess) {
+  if (hipMalloc((void**)&h->flags, 64) != hipSuccess || hipMalloc((void**)&h->red, 64) != hipSuccess ||
+      hipMalloc((void**)&h->dprm, sizeof(Params)) != hipSuccess) {
     cdg2_destroy(h);
     return fail(CDG2_ENOMEM, "hipMalloc of flag buffers failed");
   }
-  if (hipMemset(h->flags, 0, 64) != hipSuccess) {
+  if (hipMemset(h->flags, 0, 64) != hipSuccess || upload_params(h) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess) {
     cdg2_destroy(h);
-    return fail(CDG2_EHIP, "hipMemset failed");
+    return fail(CDG2_EHIP, "device initialisation failed");
   }
   *out = h;
   return CDG2_OK;
@@ -223,6 +234,7 @@ int cdg2_destroy(cdg2_handle* h) {
     if (h->stage[k]) (void)hipFree(h->stage[k]);
   if (h->flags) (void)hipFree(h->flags);
   if (h->red) (void)hipFree(h->red);
+  if (h->dprm) (void)hipFree(h->dprm);
   delete h;
   return CDG2_OK;
 }
@@ -241,6 +253,7 @@ int cdg2_set_coeffs(cdg2_handle* h, const cdg2_coeffs* c) {
   if (rc) return rc;
   h->cfg.coeffs = *c;
   coef_from(*c, &h->coef);
+  HIP_TRY(upload_params(h));
   return CDG2_OK;
 }
 

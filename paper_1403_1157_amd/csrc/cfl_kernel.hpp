@@ -11,8 +11,11 @@ namespace cdg2 {
 
 template <int D, int P, typename T, int EPW, int NT>
 __global__ void __launch_bounds__(NT)
-cfl_kernel(const Tables tb, const Geo g, const Coef cf, const T* __restrict__ U,
+cfl_kernel(const Params* __restrict__ prm, const T* __restrict__ U,
            unsigned long long* __restrict__ out3, int* __restrict__ flags) {
+  const Tables& tb = prm->tb;
+  const Geo& g = prm->g;
+  const Coef& cf = prm->cf;
   using Z = Sz<D, P>;
   constexpr int Q = Z::Q, NM = Z::NM, NQ = Z::NQ;
   constexpr int NPV = 4 + 3 * D;

@@ -196,6 +196,14 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return x * per + (x < rem ? x : rem) + b / nx;
 }
 
+// Everything a kernel reads besides the state: kept in device memory (one copy
+// per handle) so that kernels index it freely without private copies.
+struct Params {
+  Tables tb;
+  Geo g;
+  Coef cf;
+};
+
 // Flag bits reported by cdg2_sync.
 enum { FLAG_NONFINITE = 1, FLAG_DOMAIN = 2 };
 

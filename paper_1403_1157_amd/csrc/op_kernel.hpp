@@ -49,8 +49,11 @@ struct OpKernel {
 // alias out; each cell reads its own U0 entries before writing them).
 template <int D, int P, typename T, int EPW, int NT>
 __global__ void __launch_bounds__(NT)
-op_kernel(const Tables tb, const Geo g, const Coef cf, const T* __restrict__ U, const T* U0,
+op_kernel(const Params* __restrict__ prm, const T* __restrict__ U, const T* U0,
           T* out, T dt, T ca, T cb, int stage, int* __restrict__ flags) {
+  const Tables& tb = prm->tb;
+  const Geo& g = prm->g;
+  const Coef& cf = prm->cf;
   using K = OpKernel<D, P, T, EPW, NT>;
   constexpr int Q = K::Q, NM = K::NM, NQ = K::NQ, NF = K::NF, NFACE = K::NFACE, NPV = K::NPV;
   __shared__ typename K::Smem sm;
