@@ -10,7 +10,7 @@
 
 #include "../../include/cdg2.h"
 #include "cfl_kernel.hpp"
-#include "op_kernel.hpp"
+#include "es_kernel.hpp"
 #include "tables.cpp"
 
 using namespace cdg2;
@@ -116,12 +116,18 @@ struct LaunchCfg {
   static constexpr int NT = D == 3 ? 64 : 128;
 };
 
+// cells per workgroup of the (cell, species) kernel: 6 * EB threads
+template <int D, int P>
+struct EsCfg {
+  static constexpr int EB = D == 3 ? 32 : 32;
+};
+
 template <int D, int P, typename T>
 hipError_t launch_op(cdg2_handle* h, const void* U, const void* U0, void* out, double dt, double ca,
                      double cb, int stage) {
-  using L = LaunchCfg<D, P>;
-  int nb = (h->geo.E + L::EPW - 1) / L::EPW;
-  hipLaunchKernelGGL((op_kernel<D, P, T, L::EPW, L::NT>), dim3(nb), dim3(L::NT), 0, h->stream, h->dprm,
+  constexpr int EB = EsCfg<D, P>::EB;
+  int nb = (h->geo.E + EB - 1) / EB;
+  hipLaunchKernelGGL((es_kernel<D, P, T, EB>), dim3(nb), dim3(6 * EB), 0, h->stream, h->dprm,
                      (const T*)U, (const T*)U0, (T*)out, (T)dt, (T)ca, (T)cb, stage, h->flags);
   return hipGetLastError();
 }

@@ -1,0 +1,456 @@
+// CDG2 operator kernel, one thread per (cell, species).
+//
+// Same discrete operator as described in op_kernel.hpp (Section 3.1 volume and
+// face integrals, LLF convective flux, CDG2 lifting on K^-, M^{-1} = 1/|K|,
+// optional SSP-RK3 stage combination in the epilogue).  Mapping:
+//   * a workgroup owns EB consecutive cells; thread (s, el) keeps the modes and
+//     the modal residual of species s of cell el in registers;
+//   * everything linear in U is applied by that thread alone, exactly, in modal
+//     form: -a_s int grad u . grad phi (1D stiffness per axis), the face
+//     consistency / symmetry / lifting terms (tangential-modal traces of the
+//     cell and of its neighbour, whose modes the thread reads from global
+//     memory), and the linear reactions (other species' modes of the same cell);
+//   * the nonlinear terms need several species at one point; they are
+//     exchanged through LDS: the volume one layer of Gauss points (along the
+//     last axis) at a time, the faces one face direction at a time.  Point items
+//     (cell, point) evaluate w1, w2, F1, F2, alpha n c, lambda and the inflow
+//     fluxes; species threads integrate them back against their test functions.
+// Each face is evaluated from both sides (every cell treats all its faces).
+#pragma once
+
+#include "op_common.hpp"
+
+namespace cdg2 {
+
+// Sizes for D, P with chunks of Gauss points = layers along the last axis.
+template <int D, int P>
+struct EsSz {
+  using Z = Sz<D, P>;
+  static constexpr int Q = Z::Q, NM = Z::NM, NQ = Z::NQ, NF = Z::NF, NFACE = Z::NFACE;
+  static constexpr int PC = NF;            // points per layer
+  static constexpr int NVQ = 4 + 3 * D;    // n1 n2 c1 c3 | grad n1 | grad c1 | grad c3
+  static constexpr int NFQ = 14;           // face exchange: 4 values x 2 sides, 3 d_n x 2 sides
+};
+
+// LDS: one union buffer, reused by the volume layers and by the faces.
+template <int D, int P, typename T, int EB>
+struct EsSmem {
+  using S = EsSz<D, P>;
+  static constexpr int VOL = EB * S::NVQ * S::PC;
+  static constexpr int FAC = EB * S::NFQ * S::NF;
+  static constexpr int N = VOL > FAC ? VOL : FAC;
+  T buf[N];
+  int nb[EB][2 * D];
+};
+
+// (D-1)-dimensional tensor contraction of NF values (tangential / layer axes).
+template <int D, int Q, bool TR, typename T>
+__device__ __forceinline__ void tapply_lo(const T* in, T* out, const double (*M0)[CDG2_MAXQ],
+                                          const double (*M1)[CDG2_MAXQ]) {
+  if constexpr (D == 2) {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      T s = T(0);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) s += mat<TR, T>(M0, a, i) * in[i];
+      out[a] = s;
+    }
+  } else {
+    tapply<2, Q, TR, T>(in, out, M0, M1, nullptr);
+  }
+}
+
+template <int D, int P, typename T, int EB>
+__device__ __forceinline__ void es_block(const Params& prm, const T* __restrict__ U, const T* U0, T* out,
+                                         T dt, T ca, T cb, int stage, int* __restrict__ flags, int e0,
+                                         EsSmem<D, P, T, EB>& sm) {
+  using S = EsSz<D, P>;
+  constexpr int Q = S::Q, NM = S::NM, NF = S::NF, NFACE = S::NFACE, PC = S::PC, NVQ = S::NVQ;
+  constexpr int NT = 6 * EB;
+  const Tables& tb = prm.tb;
+  const Geo& g = prm.g;
+  const double* c = prm.cf.c;
+  const int tid = threadIdx.x;
+  const int s = tid / EB, el = tid % EB;
+  const int E = g.E;
+  const int e = e0 + el;
+  const bool live = e < E;
+  const size_t SE = (size_t)E * NM;
+  const T vol = T(g.vol);
+  int flag = 0;
+
+  // ---- own modes, neighbour table ------------------------------------------------
+  T u[NM], R[NM];
+  {
+    const T* src = U + s * SE + (size_t)(live ? e : 0) * NM;
+#pragma unroll
+    for (int m = 0; m < NM; ++m) u[m] = live ? src[m] : T(0);
+  }
+  for (int it = tid; it < EB * NFACE; it += NT) {
+    int l = it / NFACE, f = it % NFACE;
+    sm.nb[l][f] = e0 + l < E ? neighbour<D>(g, e0 + l, f) : -3;
+  }
+
+  // ---- linear volume terms: -a_s |K| sum_a h_a^-2 (S along a) u + linear reactions --
+  {
+    const T as = T(c[K_MU1 + s]);
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      T acc = T(0);
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const int st = ipow(Q, a);
+        const int ia = (m / st) % Q;
+        const int base = m - ia * st;
+        T sa = T(0);
+#pragma unroll
+        for (int j = 0; j < Q; ++j) sa += T(tb.S[ia][j]) * u[base + j * st];
+        acc += T(g.ih[a] * g.ih[a]) * sa;
+      }
+      R[m] = -as * vol * acc;
+    }
+    // S_lin: n1: -d1 n1; n2: -d2 n2; n3: (d1 - gamma) n1 + d2 n2; c1: f1 n3;
+    //        c2: -k c2; c3: k c2.  Other species' modes of the same cell come from
+    //        global memory (the workgroup has just read them).
+    const T* cell = U + (size_t)(live ? e : 0) * NM;
+    if (s == S_N1 || s == S_N2 || s == S_C2) {
+      const T k = -T(s == S_N1 ? c[K_D1] : s == S_N2 ? c[K_D2] : c[K_K]) * vol;
+#pragma unroll
+      for (int m = 0; m < NM; ++m) R[m] += k * u[m];
+    } else if (live) {
+      const T* a0 = cell + (s == S_N3 ? S_N1 : s == S_C1 ? S_N3 : S_C2) * SE;
+      const T k0 = T(s == S_N3 ? c[K_D1] - c[K_GAM] : s == S_C1 ? c[K_F1] : c[K_K]) * vol;
+#pragma unroll
+      for (int m = 0; m < NM; ++m) R[m] += k0 * a0[m];
+      if (s == S_N3) {
+        const T* a1 = cell + S_N2 * SE;
+        const T k1 = T(c[K_D2]) * vol;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) R[m] += k1 * a1[m];
+      }
+    }
+  }
+
+  // ---- nonlinear volume terms, one layer of Gauss points at a time ------------------
+  // producer quantity slots: 0 n1, 1 n2, 2 c1, 3 c3, 4+a grad n1, 4+D+a grad c1,
+  // 4+2D+a grad c3.  After the point pass: slots 0..D-1 F1 (weighted, /h_a),
+  // D..2D-1 F2, 2D alpha-term.
+  const int prod = s == S_N1 ? 0 : s == S_N2 ? 1 : s == S_C1 ? 2 : s == S_C3 ? 3 : -1;
+  const bool grads = s == S_N1 || s == S_C1 || s == S_C3;
+  const int gslot = s == S_N1 ? 4 : s == S_C1 ? 4 + D : 4 + 2 * D;
+  T* V = sm.buf;   // [EB][NVQ][PC]
+  constexpr int LA = D - 1;   // layer axis
+  constexpr int LST = ipow(Q, D - 1);
+  const double(*Bt0)[CDG2_MAXQ] = tb.B;
+  for (int lc = 0; lc < Q; ++lc) {
+    __syncthreads();
+    if (prod >= 0) {
+      // contract the layer axis with row lc of B (values, in-layer derivatives) and Bd
+      T tv[NF], td[NF], o[NF];
+#pragma unroll
+      for (int r = 0; r < NF; ++r) {
+        T a0 = T(0), a1 = T(0);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          a0 += T(tb.B[lc][k]) * u[r + LST * k];
+          a1 += T(tb.Bd[lc][k]) * u[r + LST * k];
+        }
+        tv[r] = a0;
+        td[r] = a1;
+      }
+      tapply_lo<D, Q, false, T>(tv, o, Bt0, Bt0);
+#pragma unroll
+      for (int q = 0; q < PC; ++q) V[(el * NVQ + prod) * PC + q] = o[q];
+      if (grads) {
+#pragma unroll
+        for (int a = 0; a < D - 1; ++a) {
+          tapply_lo<D, Q, false, T>(tv, o, a == 0 ? tb.Bd : tb.B, a == 1 ? tb.Bd : tb.B);
+#pragma unroll
+          for (int q = 0; q < PC; ++q) V[(el * NVQ + gslot + a) * PC + q] = o[q] * T(g.ih[a]);
+        }
+        tapply_lo<D, Q, false, T>(td, o, Bt0, Bt0);
+#pragma unroll
+        for (int q = 0; q < PC; ++q) V[(el * NVQ + gslot + LA) * PC + q] = o[q] * T(g.ih[LA]);
+      }
+    }
+    __syncthreads();
+    // point pass: chemotactic fluxes and the alpha reaction term, weighted
+    for (int it = tid; it < EB * PC; it += NT) {
+      const int l = it / PC, q = it % PC;
+      T* v = V + l * NVQ * PC + q;
+      const T n1 = v[0], n2 = v[PC], c1 = v[2 * PC], c3 = v[3 * PC];
+      const T d11 = c1 + T(c[K_XT11]), d13 = c3 + T(c[K_XT13]), d21 = c1 + T(c[K_XT21]),
+              d22 = n1 + T(c[K_XT22]);
+      if (e0 + l < E && !(d11 > T(0) && d13 > T(0) && d21 > T(0) && d22 > T(0))) flag |= FLAG_DOMAIN;
+      const T k11 = T(c[K_X011]) / d11, k13 = T(c[K_X013]) / d13, k21 = T(c[K_X021]) / d21,
+              k22 = T(c[K_X022]) / d22;
+      // weight of the point: |K| w_q (layer index lc along the last axis)
+      T wt = vol * T(tb.w[lc]);
+      if constexpr (D == 2) {
+        wt *= T(tb.w[q]);
+      } else {
+        wt *= T(tb.w[q % Q]) * T(tb.w[q / Q]);
+      }
+      T F1[D], F2[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const T gn1 = v[(4 + a) * PC], gc1 = v[(4 + D + a) * PC], gc3 = v[(4 + 2 * D + a) * PC];
+        F1[a] = n1 * (k11 * gc1 + k13 * gc3) * wt * T(g.ih[a]);
+        F2[a] = n2 * (k21 * gc1 - k22 * gn1) * wt * T(g.ih[a]);
+      }
+      const T rc = -(T(c[K_AL1]) * n1 + T(c[K_AL2]) * n2) * c1 * wt;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        v[a * PC] = F1[a];
+        v[(D + a) * PC] = F2[a];
+      }
+      v[2 * D * PC] = rc;
+    }
+    __syncthreads();
+    // test integration of this layer: n1, n2 (F . grad phi), c1 (alpha term phi)
+    if (s == S_N1 || s == S_N2 || s == S_C1) {
+      const int base = s == S_N2 ? D : 0;
+      T r[NF], acc[NF];
+      if (s == S_C1) {
+#pragma unroll
+        for (int q = 0; q < PC; ++q) r[q] = V[(el * NVQ + 2 * D) * PC + q];
+        tapply_lo<D, Q, true, T>(r, acc, Bt0, Bt0);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+#pragma unroll
+          for (int m = 0; m < NF; ++m) R[m + LST * k] += T(tb.B[lc][k]) * acc[m];
+      } else {
+        // in-layer derivative directions: phi along the layer axis is B[lc][k]
+        T sum[NF];
+#pragma unroll
+        for (int m = 0; m < NF; ++m) sum[m] = T(0);
+#pragma unroll
+        for (int a = 0; a < D - 1; ++a) {
+#pragma unroll
+          for (int q = 0; q < PC; ++q) r[q] = V[(el * NVQ + base + a) * PC + q];
+          tapply_lo<D, Q, true, T>(r, acc, a == 0 ? tb.Bd : tb.B, a == 1 ? tb.Bd : tb.B);
+#pragma unroll
+          for (int m = 0; m < NF; ++m) sum[m] += acc[m];
+        }
+#pragma unroll
+        for (int q = 0; q < PC; ++q) r[q] = V[(el * NVQ + base + LA) * PC + q];
+        tapply_lo<D, Q, true, T>(r, acc, Bt0, Bt0);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+#pragma unroll
+          for (int m = 0; m < NF; ++m)
+            R[m + LST * k] += T(tb.B[lc][k]) * sum[m] + T(tb.Bd[lc][k]) * acc[m];
+      }
+    }
+  }
+
+  // ---- faces ------------------------------------------------------------------------
+  const T as = T(c[K_MU1 + s]);
+  const bool diss = !(g.llf_cells && s > S_N2);
+  // face exchange slots (x NF): 0..3 values n1 n2 c1 c3 own, 4..7 same neighbour,
+  // 8..10 d_a n1 c1 c3 own, 11..13 neighbour.  After the point pass: 0 lambda/2,
+  // 1 -F1.n_o/2 sum, 2 -F2.n_o/2 sum, 3..5 inflow fluxes n1, n2, c2 (boundary).
+  T* Fx = sm.buf;
+  const int vslot = prod;   // value slot of this species (or -1)
+  const int dslot = s == S_N1 ? 8 : s == S_C1 ? 9 : s == S_C3 ? 10 : -1;
+  // the face axis is unrolled (a compile-time constant, so that the register
+  // arrays u and R are indexed statically); the two sides of an axis are not
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll 1
+  for (int sg = 0; sg < 2; ++sg) {
+    const int f = 2 * a + sg;
+    __syncthreads();
+    const int nb = sm.nb[el][f];
+    // tangential-modal traces: value / d_a of own and neighbour, accurate jump
+    T uo[NF], duo[NF], un[NF], dun[NF], jm[NF];
+#pragma unroll
+    for (int J = 0; J < NF; ++J) {
+      T a0 = T(0), a1 = T(0);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const T v = u[face_mode<D, Q>(a, i, J)];
+        a0 += T(tb.E[sg][i]) * v;
+        a1 += T(tb.dE[sg][i]) * v;
+      }
+      uo[J] = a0;
+      duo[J] = a1 * T(g.ih[a]);
+      un[J] = T(0);
+      dun[J] = T(0);
+      jm[J] = T(0);
+    }
+    if (nb >= 0) {
+      const T* un_src = U + s * SE + (size_t)nb * NM;
+#pragma unroll
+      for (int J = 0; J < NF; ++J) {
+        T a0 = T(0), a1 = T(0), a2 = T(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const int m = face_mode<D, Q>(a, i, J);
+          const T v = un_src[m];
+          a0 += T(tb.E[1 - sg][i]) * v;
+          a1 += T(tb.dE[1 - sg][i]) * v;
+          // u_o - u_n formed mode by mode: the i = 0 terms (value 1 at both ends)
+          // cancel exactly
+          a2 += i == 0 ? u[m] - v : T(tb.E[sg][i]) * u[m] - T(tb.E[1 - sg][i]) * v;
+        }
+        un[J] = a0;
+        dun[J] = a1 * T(g.ih[a]);
+        jm[J] = a2;
+      }
+    }
+    // publish point values needed by the face point pass
+    const int b0 = a == 0 ? 1 : 0, b1 = a == 2 ? 1 : 2;   // tangential axes
+    const double(*Tb0)[CDG2_MAXQ] = tb.B;
+    if (vslot >= 0) {
+      T o[NF];
+      tapply_lo<D, Q, false, T>(uo, o, Tb0, Tb0);
+#pragma unroll
+      for (int t = 0; t < NF; ++t) Fx[(el * 14 + vslot) * NF + t] = o[t];
+      tapply_lo<D, Q, false, T>(un, o, Tb0, Tb0);
+#pragma unroll
+      for (int t = 0; t < NF; ++t) Fx[(el * 14 + 4 + vslot) * NF + t] = o[t];
+    }
+    if (dslot >= 0) {
+      T o[NF];
+      tapply_lo<D, Q, false, T>(duo, o, Tb0, Tb0);
+#pragma unroll
+      for (int t = 0; t < NF; ++t) Fx[(el * 14 + dslot) * NF + t] = o[t];
+      tapply_lo<D, Q, false, T>(dun, o, Tb0, Tb0);
+#pragma unroll
+      for (int t = 0; t < NF; ++t) Fx[(el * 14 + dslot + 3) * NF + t] = o[t];
+    }
+    __syncthreads();
+    // face point pass
+    for (int it = tid; it < EB * NF; it += NT) {
+      const int l = it / NF, t = it % NF;
+      T* x = Fx + l * 14 * NF + t;
+      const int nbl = sm.nb[l][f];
+      const T c1o = x[2 * NF];
+      if (nbl >= 0) {
+        const T so = sg ? T(1) : T(-1);
+        const T n1o = x[0], n2o = x[NF], c3o = x[3 * NF];
+        const T n1n = x[4 * NF], n2n = x[5 * NF], c1n = x[6 * NF], c3n = x[7 * NF];
+        const T dn1o = x[8 * NF], dc1o = x[9 * NF], dc3o = x[10 * NF];
+        const T dn1n = x[11 * NF], dc1n = x[12 * NF], dc3n = x[13 * NF];
+        const T t11 = T(c[K_XT11]), t13 = T(c[K_XT13]), t21 = T(c[K_XT21]), t22 = T(c[K_XT22]);
+        const T d11o = c1o + t11, d13o = c3o + t13, d21o = c1o + t21, d22o = n1o + t22;
+        const T d11n = c1n + t11, d13n = c3n + t13, d21n = c1n + t21, d22n = n1n + t22;
+        if (e0 + l < E && !(d11o > T(0) && d13o > T(0) && d21o > T(0) && d22o > T(0) &&
+                            d11n > T(0) && d13n > T(0) && d21n > T(0) && d22n > T(0)))
+          flag |= FLAG_DOMAIN;
+        const T w1o = so * (T(c[K_X011]) * dc1o / d11o + T(c[K_X013]) * dc3o / d13o);
+        const T w2o = so * (T(c[K_X021]) * dc1o / d21o - T(c[K_X022]) * dn1o / d22o);
+        const T w1n = so * (T(c[K_X011]) * dc1n / d11n + T(c[K_X013]) * dc3n / d13n);
+        const T w2n = so * (T(c[K_X021]) * dc1n / d21n - T(c[K_X022]) * dn1n / d22n);
+        const T lam = fmax(fmax(fabs(w1o), fabs(w2o)), fmax(fabs(w1n), fabs(w2n)));
+        x[0] = T(0.5) * lam;
+        x[NF] = -T(0.5) * (n1o * w1o + n1n * w1n);
+        x[2 * NF] = -T(0.5) * (n2o * w2o + n2n * w2n);
+      } else {
+        T q1 = T(0), q2 = T(0), q5 = T(0);
+        if (nbl == -1) {
+          if (c1o - T(c[K_C1S]) > T(0)) q1 = T(c[K_MU1] * c[K_BE1]);
+          const int tb0 = t % Q;
+          const double xc = (cell_coord<D>(g, e0 + l, b0) + tb.x[tb0]) * g.h[b0];
+          if (xc >= g.g1in[0] && xc <= g.g1in[1]) q5 = T(c[K_NU2] * c[K_SIG]);
+        } else if (nbl == -2) {
+          if (c1o - T(c[K_C1SS]) > T(0)) q2 = T(c[K_MU2] * c[K_BE2]);
+        }
+        x[0] = T(0);
+        x[NF] = T(0);
+        x[2 * NF] = T(0);
+        x[3 * NF] = q1;
+        x[4 * NF] = q2;
+        x[5 * NF] = q5;
+      }
+    }
+    __syncthreads();
+    // species pass: nonlinear flux at the points, projected on the tangential modes,
+    // plus the linear face terms; spread onto the normal modes
+    {
+      T gp[NF], gh[NF];
+      const T* x = Fx + el * 14 * NF;
+      if (nb >= 0) {
+        T jp[NF];
+        tapply_lo<D, Q, false, T>(jm, jp, Tb0, Tb0);
+#pragma unroll
+        for (int t = 0; t < NF; ++t) {
+          T v = diss ? -x[t] * jp[t] : T(0);
+          if (s == S_N1) v += x[NF + t];
+          if (s == S_N2) v += x[2 * NF + t];
+          gp[t] = v;
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < NF; ++t) {
+          gp[t] = s == S_N1 ? x[3 * NF + t] : s == S_N2 ? x[4 * NF + t] : s == S_C2 ? x[5 * NF + t] : T(0);
+        }
+      }
+      // weights of the tangential Gauss points
+#pragma unroll
+      for (int t = 0; t < NF; ++t) {
+        if constexpr (D == 2) {
+          gp[t] *= T(tb.w[t]);
+        } else {
+          gp[t] *= T(tb.w[t % Q]) * T(tb.w[t / Q]);
+        }
+      }
+      tapply_lo<D, Q, true, T>(gp, gh, Tb0, Tb0);
+      const T ar = T(g.area[a]);
+      const T so = sg ? T(1) : T(-1);
+      const T pen = T(g.chi_e * tb.liftc * g.ih[a]) * as;
+      T G[NF], H[NF];
+#pragma unroll
+      for (int J = 0; J < NF; ++J) {
+        T lin = T(0), hh = T(0);
+        if (nb >= 0) {
+          lin = so * T(0.5) * as * (duo[J] + dun[J]) - pen * jm[J];
+          hh = T(0.5) * as * jm[J] * so * T(g.ih[a]);
+        }
+        G[J] = ar * (lin + gh[J]);
+        H[J] = ar * hh;
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+#pragma unroll
+        for (int J = 0; J < NF; ++J)
+          R[face_mode<D, Q>(a, i, J)] += T(tb.E[sg][i]) * G[J] + T(tb.dE[sg][i]) * H[J];
+    }
+  }
+
+  // ---- M^{-1}, stage combination, store ---------------------------------------------
+  if (live) {
+    const T ivol = T(1.0 / g.vol);
+    T* dst = out + s * SE + (size_t)e * NM;
+    if (stage == 0) {
+#pragma unroll
+      for (int m = 0; m < NM; ++m) {
+        const T v = R[m] * ivol;
+        if (!isfinite(v)) flag |= FLAG_NONFINITE;
+        dst[m] = v;
+      }
+    } else {
+      const T* u0 = U0 + s * SE + (size_t)e * NM;
+#pragma unroll
+      for (int m = 0; m < NM; ++m) {
+        T v = cb * (u[m] + dt * (R[m] * ivol));
+        if (ca != T(0)) v += ca * u0[m];
+        if (!isfinite(v)) flag |= FLAG_NONFINITE;
+        dst[m] = v;
+      }
+    }
+  }
+  if (flag) atomicOr(flags, flag);
+}
+
+template <int D, int P, typename T, int EB>
+__global__ void __launch_bounds__(6 * EB)
+es_kernel(const Params* __restrict__ prm, const T* __restrict__ U, const T* U0, T* out, T dt, T ca, T cb,
+          int stage, int* __restrict__ flags) {
+  __shared__ EsSmem<D, P, T, EB> sm;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  es_block<D, P, T, EB>(*prm, U, U0, out, dt, ca, cb, stage, flags, blk * EB, sm);
+}
+
+}  // namespace cdg2
