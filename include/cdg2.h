@@ -135,6 +135,27 @@ int cdg2_sync(cdg2_handle* h);
 /* Spectral constant rho_hat used by cdg2_max_dt (host-computed at create). */
 double cdg2_rho_hat(const cdg2_handle* h);
 
+/* Adjoint of the operator (the transposed Jacobian J = d f / d U of f = M^{-1}
+ * L_h, Sections 3.1-3.2): JTw = J(U)^T w.  U, w, JTw: device buffers of
+ * cdg2_num_dofs entries; JTw must not overlap U or w.  If dtheta is not NULL it
+ * is a HOST array of CDG2_NDIFF doubles that receives d (w . f(U)) / d theta_j
+ * for the 21 differentiable coefficients (order of cdg2_coeffs); the call then
+ * waits for the device.  Non-smooth points: d|x|/dx = sign(x) (0 at 0), the max
+ * of the LLF speed takes the first maximiser, the inflow Heaviside has
+ * derivative 0.  Parameter sums are reduced in a fixed order (deterministic). */
+int cdg2_apply_adjoint(cdg2_handle* h, const void* U, const void* w, void* JTw, double* dtheta);
+
+/* Discrete adjoint of one SSP-RK3 step of size dt started from U_n: given
+ * lam_np1 = dL/dU^{n+1}, writes lam_n = dL/dU^n:
+ *   lam2 = 2/3 lam3 + 2/3 dt J(U2)^T lam3,  lam1 = 1/4 lam2 + 1/4 dt J(U1)^T lam2,
+ *   lam_n = 1/3 lam3 + 3/4 lam2 + lam1 + dt J(U_n)^T lam1,
+ * with U1, U2 recomputed from U_n into the stage buffers.  lam_n may alias
+ * lam_np1 (in place) but not U_n.  If dtheta_acc (HOST, CDG2_NDIFF doubles) is
+ * not NULL, 2/3 dt df(U2)/dtheta^T lam3 + 1/4 dt df(U1)/dtheta^T lam2 +
+ * dt df(U_n)/dtheta^T lam1 is ADDED to it and the call waits for the device. */
+int cdg2_rk_step_adjoint(cdg2_handle* h, const void* U_n, const void* lam_np1, void* lam_n, double dt,
+                         double* dtheta_acc);
+
 /* Thread-local message of the last error. */
 const char* cdg2_last_error(void);
 

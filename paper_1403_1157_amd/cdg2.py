@@ -72,10 +72,13 @@ def lib():
     L.cdg2_sync.argtypes = [P]
     L.cdg2_rho_hat.argtypes = [P]
     L.cdg2_rho_hat.restype = _d
+    L.cdg2_apply_adjoint.argtypes = [P, P, P, P, ctypes.POINTER(_d)]
+    L.cdg2_rk_step_adjoint.argtypes = [P, P, P, P, _d, ctypes.POINTER(_d)]
     L.cdg2_last_error.argtypes = []
     L.cdg2_last_error.restype = ctypes.c_char_p
     for name in ("cdg2_create", "cdg2_destroy", "cdg2_set_stream", "cdg2_set_coeffs",
-                 "cdg2_apply_operator", "cdg2_rk_step", "cdg2_max_dt", "cdg2_sync"):
+                 "cdg2_apply_operator", "cdg2_rk_step", "cdg2_max_dt", "cdg2_sync",
+                 "cdg2_apply_adjoint", "cdg2_rk_step_adjoint"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -153,6 +156,25 @@ def cdg2_max_dt(h, U_ptr: int, cfl: float) -> float:
     return dt.value
 
 
+def cdg2_apply_adjoint(h, U_ptr: int, w_ptr: int, out_ptr: int, want_theta: bool = False):
+    """Returns the 21 parameter derivatives (list) when want_theta, else None."""
+    arr = (_d * 21)() if want_theta else None
+    _check(lib().cdg2_apply_adjoint(h, ctypes.c_void_p(U_ptr), ctypes.c_void_p(w_ptr),
+                                    ctypes.c_void_p(out_ptr), arr))
+    return list(arr) if want_theta else None
+
+
+def cdg2_rk_step_adjoint(h, Un_ptr: int, lam_np1_ptr: int, lam_n_ptr: int, dt: float, dtheta_acc=None):
+    """dtheta_acc: None or a numpy float64 array of 21 entries, added to in place."""
+    arr = None
+    if dtheta_acc is not None:
+        arr = (_d * 21)(*[float(x) for x in dtheta_acc])
+    _check(lib().cdg2_rk_step_adjoint(h, ctypes.c_void_p(Un_ptr), ctypes.c_void_p(lam_np1_ptr),
+                                      ctypes.c_void_p(lam_n_ptr), float(dt), arr))
+    if dtheta_acc is not None:
+        dtheta_acc[:] = list(arr)
+
+
 def cdg2_sync(h) -> None:
     _check(lib().cdg2_sync(h))
 
@@ -204,6 +226,19 @@ class Operator:
     def max_dt(self, U: torch.Tensor, cfl: float = 0.9) -> float:
         self._stream()
         return cdg2_max_dt(self.h, self._arg(U), cfl)
+
+    def apply_adjoint(self, U, w, out=None, want_theta=False):
+        """J(U)^T w (and d(w . f(U))/d theta for the 21 coefficients if asked)."""
+        if out is None:
+            out = torch.empty_like(U)
+        self._stream()
+        th = cdg2_apply_adjoint(self.h, self._arg(U), self._arg(w), self._arg(out), want_theta)
+        return (out, th) if want_theta else out
+
+    def rk_step_adjoint(self, U_n, lam_np1, lam_n, dt, dtheta_acc=None):
+        self._stream()
+        cdg2_rk_step_adjoint(self.h, self._arg(U_n), self._arg(lam_np1), self._arg(lam_n), dt, dtheta_acc)
+        return lam_n
 
     def set_coeffs(self, coeffs: dict) -> None:
         cdg2_set_coeffs(self.h, coeffs)

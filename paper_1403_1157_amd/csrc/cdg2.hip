@@ -10,6 +10,7 @@
 
 #include "../../include/cdg2.h"
 #include "cfl_kernel.hpp"
+#include "adj_kernel.hpp"
 #include "es_kernel.hpp"
 #include "tables.cpp"
 
@@ -48,6 +49,10 @@ struct cdg2_handle {
   void* stage[2] = {nullptr, nullptr};
   int* flags = nullptr;
   unsigned long long* red = nullptr;
+  void* adj[2] = {nullptr, nullptr};   // adjoint stage buffers (allocated on first use)
+  double* part = nullptr;              // per-workgroup parameter partials
+  double* dth = nullptr;               // device accumulator of parameter derivatives
+  int nblk_adj = 0;
   hipStream_t stream = nullptr;
   double rho_hat = 0.0;
 };
@@ -170,6 +175,61 @@ hipError_t dispatch_cfl(cdg2_handle* h, const void* U) {
   return hipErrorInvalidValue;
 }
 
+template <int D, int P>
+struct AdjCfg {
+  static constexpr int EB = 32;
+};
+
+template <int D, int P, typename T>
+hipError_t launch_adj(cdg2_handle* h, const void* U, const void* W, void* out, double cw, double cj,
+                      const void* X2, double c2, const void* X3, double c3, int want_theta) {
+  constexpr int EB = AdjCfg<D, P>::EB;
+  int nb = (h->geo.E + EB - 1) / EB;
+  hipLaunchKernelGGL((adj_kernel<D, P, T, EB>), dim3(nb), dim3(6 * EB), 0, h->stream, h->dprm, (const T*)U,
+                     (const T*)W, (T*)out, (T)cw, (T)cj, (const T*)X2, (T)c2, (const T*)X3, (T)c3, h->part,
+                     want_theta, h->flags);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !want_theta) return e;
+  hipLaunchKernelGGL(theta_reduce_kernel, dim3(CDG2_NDIFF), dim3(256), 0, h->stream, (const double*)h->part, nb,
+                     h->dth);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_adj(cdg2_handle* h, const void* U, const void* W, void* out, double cw, double cj,
+                        const void* X2, double c2, const void* X3, double c3, int want_theta) {
+  switch (h->dim * 10 + h->p) {
+    case 21: return launch_adj<2, 1, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta);
+    case 22: return launch_adj<2, 2, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta);
+    case 23: return launch_adj<2, 3, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta);
+    case 24: return launch_adj<2, 4, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta);
+    case 31: return launch_adj<3, 1, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta);
+    case 32: return launch_adj<3, 2, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta);
+    case 33: return launch_adj<3, 3, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t run_adj(cdg2_handle* h, const void* U, const void* W, void* out, double cw, double cj,
+                   const void* X2, double c2, const void* X3, double c3, int want_theta) {
+  return h->fp32 ? dispatch_adj<float>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta)
+                 : dispatch_adj<double>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta);
+}
+
+// Adjoint buffers, allocated on the first adjoint call.
+int ensure_adjoint(cdg2_handle* h) {
+  if (h->part) return CDG2_OK;
+  size_t bytes = h->ndof * (h->fp32 ? 4 : 8);
+  int nb = (h->geo.E + 31) / 32;
+  for (int k = 0; k < 2; ++k)
+    if (hipMalloc(&h->adj[k], bytes) != hipSuccess) return fail(CDG2_ENOMEM, "hipMalloc of adjoint buffers failed");
+  if (hipMalloc((void**)&h->dth, 64 * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&h->part, (size_t)nb * CDG2_NDIFF * sizeof(double)) != hipSuccess)
+    return fail(CDG2_ENOMEM, "hipMalloc of parameter buffers failed");
+  h->nblk_adj = nb;
+  return CDG2_OK;
+}
+
 hipError_t run_op(cdg2_handle* h, const void* U, const void* U0, void* out, double dt, double ca, double cb,
                   int stage) {
   return h->fp32 ? dispatch_op<float>(h, U, U0, out, dt, ca, cb, stage)
@@ -241,6 +301,10 @@ int cdg2_destroy(cdg2_handle* h) {
   if (h->flags) (void)hipFree(h->flags);
   if (h->red) (void)hipFree(h->red);
   if (h->dprm) (void)hipFree(h->dprm);
+  for (int k = 0; k < 2; ++k)
+    if (h->adj[k]) (void)hipFree(h->adj[k]);
+  if (h->part) (void)hipFree(h->part);
+  if (h->dth) (void)hipFree(h->dth);
   delete h;
   return CDG2_OK;
 }
@@ -286,6 +350,50 @@ int cdg2_rk_step(cdg2_handle* h, void* U, double dt, int nsteps) {
     HIP_TRY(run_op(h, U, nullptr, h->stage[0], dt, 0.0, 1.0, 1));
     HIP_TRY(run_op(h, h->stage[0], U, h->stage[1], dt, 0.75, 0.25, 2));
     HIP_TRY(run_op(h, h->stage[1], U, U, dt, 1.0 / 3.0, 2.0 / 3.0, 3));
+  }
+  return CDG2_OK;
+}
+
+int cdg2_apply_adjoint(cdg2_handle* h, const void* U, const void* w, void* JTw, double* dtheta) {
+  if (!h || !U || !w || !JTw) return fail(CDG2_EINVAL, "NULL argument");
+  size_t bytes = h->ndof * (h->fp32 ? 4 : 8);
+  if (overlap(JTw, U, bytes) || overlap(JTw, w, bytes)) return fail(CDG2_EINVAL, "JTw overlaps U or w");
+  int rc = ensure_adjoint(h);
+  if (rc) return rc;
+  if (dtheta) HIP_TRY(hipMemsetAsync(h->dth, 0, CDG2_NDIFF * sizeof(double), h->stream));
+  HIP_TRY(run_adj(h, U, w, JTw, 0.0, 1.0, nullptr, 0.0, nullptr, 0.0, dtheta != nullptr));
+  if (dtheta) {
+    HIP_TRY(hipMemcpyAsync(dtheta, h->dth, CDG2_NDIFF * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+  }
+  return CDG2_OK;
+}
+
+int cdg2_rk_step_adjoint(cdg2_handle* h, const void* U_n, const void* lam_np1, void* lam_n, double dt,
+                         double* dtheta_acc) {
+  if (!h || !U_n || !lam_np1 || !lam_n) return fail(CDG2_EINVAL, "NULL argument");
+  if (!std::isfinite(dt)) return fail(CDG2_EINVAL, "dt is not finite");
+  size_t bytes = h->ndof * (h->fp32 ? 4 : 8);
+  if (overlap(lam_n, U_n, bytes)) return fail(CDG2_EINVAL, "lam_n overlaps U_n");
+  int rc = ensure_adjoint(h);
+  if (rc) return rc;
+  const int th = dtheta_acc != nullptr;
+  if (th) HIP_TRY(hipMemsetAsync(h->dth, 0, CDG2_NDIFF * sizeof(double), h->stream));
+  // forward stages of the step, recomputed from U_n
+  HIP_TRY(run_op(h, U_n, nullptr, h->stage[0], dt, 0.0, 1.0, 1));
+  HIP_TRY(run_op(h, h->stage[0], U_n, h->stage[1], dt, 0.75, 0.25, 2));
+  // reverse sweep of the Shu-Osher stages
+  //   lam2 = 2/3 lam3 + 2/3 dt J(U2)^T lam3
+  //   lam1 = 1/4 lam2 + 1/4 dt J(U1)^T lam2
+  //   lam_n = 1/3 lam3 + 3/4 lam2 + lam1 + dt J(U_n)^T lam1
+  HIP_TRY(run_adj(h, h->stage[1], lam_np1, h->adj[0], 2.0 / 3.0, 2.0 / 3.0 * dt, nullptr, 0.0, nullptr, 0.0, th));
+  HIP_TRY(run_adj(h, h->stage[0], h->adj[0], h->adj[1], 0.25, 0.25 * dt, nullptr, 0.0, nullptr, 0.0, th));
+  HIP_TRY(run_adj(h, U_n, h->adj[1], lam_n, 1.0, dt, lam_np1, 1.0 / 3.0, h->adj[0], 0.75, th));
+  if (th) {
+    double tmp[CDG2_NDIFF];
+    HIP_TRY(hipMemcpyAsync(tmp, h->dth, sizeof tmp, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int j = 0; j < CDG2_NDIFF; ++j) dtheta_acc[j] += tmp[j];
   }
   return CDG2_OK;
 }

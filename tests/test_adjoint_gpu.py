@@ -1,0 +1,181 @@
+"""GPU parity of the hand-written adjoint (transposed Jacobian, SSP-RK3 step
+adjoint, checkpointed gradient) against the oracle's autograd, and gradient
+checks by central finite differences of the GPU forward operator."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.cdg2_oracle import Config, Oracle, coeff_vector
+from parity_util import TOL, assert_close, make_case
+from paper_1403_1157_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def strong():
+    c = inputs.adjoint_coeffs()
+    c.update(chi0_11=0.05, chi0_13=0.03, chi0_21=0.04, chi0_22=0.02)
+    return c
+
+
+def gpu_op(cfg):
+    from paper_1403_1157_amd.cdg2 import Operator
+    return Operator(cfg.dim, cfg.n, cfg.order, cfg.coeffs, wall_axis=cfg.wall_axis,
+                    llf_mode=cfg.llf_mode, gamma1_in=cfg.gamma1_in)
+
+
+def theta_close(g, o, tol):
+    g = np.asarray(g)
+    o = np.asarray(o)
+    scale = np.abs(o).max()
+    err = np.abs(g - o)
+    ok = err <= tol * np.maximum(np.abs(o), 1e-3 * scale)
+    assert ok.all(), f"theta mismatch: worst {np.max(err / np.maximum(np.abs(o), 1e-3 * scale)):.3e} at {np.argmax(err)}"
+
+
+ADJ_CASES = [(2, (6, 5), 1, "all"), (2, (8, 7), 2, "all"), (2, (5, 6), 3, "cells"), (2, (4, 5), 4, "all"),
+             (3, (4, 3, 4), 1, "all"), (3, (4, 4, 3), 2, "all")]
+
+
+@pytest.mark.parametrize("dim,n,p,mode", ADJ_CASES)
+def test_apply_adjoint_parity(dim, n, p, mode):
+    """J(U)^T w and d(w . f)/d theta against the oracle's vector-Jacobian product."""
+    c = strong()
+    c.update(c1_star=0.45, c1_sstar=0.55, sigma=0.3)          # inflow switches active
+    U, cfg = make_case(dim, n, p, key=(3,), coeffs=c, llf_mode=mode, gamma1_in=(0.2, 0.7))
+    o = Oracle(cfg)
+    g = torch.Generator().manual_seed(p)
+    w = torch.randn(U.shape, generator=g, dtype=torch.float64)
+    th = coeff_vector(c).clone().requires_grad_(True)
+    X = U.clone().requires_grad_(True)
+    (o.apply(X, th) * w).sum().backward()
+    op = gpu_op(cfg)
+    out, dth = op.apply_adjoint(U.to(DEV), w.to(DEV), want_theta=True)
+    op.sync()
+    print(f"[adjoint] d{dim} {n} p{p} {mode}", flush=True)
+    assert_close(out, X.grad, TOL["fp64"], "J^T w")
+    theta_close(dth, th.grad[:21].numpy(), 1e-11)
+
+
+@pytest.mark.parametrize("dim,n,p", [(2, (8, 6), 2), (2, (5, 5), 3), (3, (4, 3, 3), 2)])
+def test_rk_step_adjoint_parity(dim, n, p):
+    c = strong()
+    U, cfg = make_case(dim, n, p, key=(4,), coeffs=c)
+    o = Oracle(cfg)
+    dt = o.max_dt(U, 0.9)
+    g = torch.Generator().manual_seed(7)
+    lam = torch.randn(U.shape, generator=g, dtype=torch.float64)
+    th = coeff_vector(c).clone().requires_grad_(True)
+    X = U.clone().requires_grad_(True)
+    (o.rk_step(X, dt, 1, theta=th) * lam).sum().backward()
+    op = gpu_op(cfg)
+    lam_d = lam.to(DEV)
+    dth = np.zeros(21)
+    op.rk_step_adjoint(U.to(DEV), lam_d, lam_d, dt, dth)     # in place
+    op.sync()
+    assert_close(lam_d, X.grad, TOL["fp64"], "RK step adjoint")
+    theta_close(dth, th.grad[:21].numpy(), 1e-11)
+
+
+def test_checkpointed_gradient_matches_oracle():
+    """Gradient of the mismatch loss through 12 steps (checkpoints every 5) against
+    the oracle's autograd gradient through the same steps."""
+    from paper_1403_1157_amd.autograd import CDG2RK, mismatch_loss, theta_of
+    c = strong()
+    U, cfg = make_case(2, (10, 8), 2, key=(4,), coeffs=c)
+    o = Oracle(cfg)
+    dt = o.max_dt(U, 0.9)
+    target = Oracle(Config(dim=2, n=(10, 8), order=2, coeffs=inputs.adjoint_target_coeffs())).rk_step(U, dt, 12)
+    # oracle reference
+    th = coeff_vector(c).clone().requires_grad_(True)
+    X = U.clone().requires_grad_(True)
+    UT = o.rk_step(X, dt, 12, theta=th)
+    d = UT[[0, 5]] - target[[0, 5]]
+    (0.5 * o.vol * (d * d).sum()).backward()
+    # GPU
+    op = gpu_op(cfg)
+    U0 = U.to(DEV).requires_grad_(True)
+    thg = theta_of(c).requires_grad_(True)
+    UTg = CDG2RK.apply(U0, thg, op, c, dt, 12, 5)
+    L = mismatch_loss(UTg, target.to(DEV), o.vol)
+    L.backward()
+    assert_close(UTg.detach(), UT.detach(), TOL["fp64"], "forward")
+    assert_close(U0.grad, X.grad, 1e-11, "dL/dU0")
+    theta_close(thg.grad.numpy(), th.grad[:21].numpy(), 1e-10)
+
+
+def _loss_fd_setup(n=(32, 32), steps=40, ckpt=20):
+    from paper_1403_1157_amd.cdg2 import Operator
+    c = inputs.adjoint_coeffs()
+    U = torch.from_numpy(inputs.initial_modes(2, n, 2, (4,))).to(DEV)
+    op = Operator(2, n, 2, c)
+    dt = op.max_dt(U, 0.9)
+    tgt = U.clone()
+    opt = Operator(2, n, 2, inputs.adjoint_target_coeffs())
+    opt.rk_step(tgt, dt, steps)
+    opt.sync()
+    vol = 1.0 / (n[0] * n[1])
+    return c, U, op, dt, tgt, vol, steps, ckpt
+
+
+def test_gradient_vs_central_finite_differences():
+    """Adjoint gradient of the mismatch loss against central differences (step
+    1e-6, relative) of the GPU forward run for every coefficient and for random
+    directions of the initial state: agreement within 1e-6 relative wherever the
+    difference quotient resolves the derivative (|grad| > 1e3 x its rounding
+    resolution sigma / h, sigma = largest second difference of the loss values);
+    elsewhere agreement within that resolution."""
+    from paper_1403_1157_amd.autograd import CDG2RK, coeffs_with, mismatch_loss, theta_of
+    c, U, op, dt, tgt, vol, steps, ckpt = _loss_fd_setup()
+    U0 = U.clone().requires_grad_(True)
+    th = theta_of(c).requires_grad_(True)
+    L = mismatch_loss(CDG2RK.apply(U0, th, op, c, dt, steps, ckpt), tgt, vol)
+    L.backward()
+
+    def loss_at(theta, Uinit):
+        op.set_coeffs(coeffs_with(c, theta))
+        X = Uinit.clone()
+        op.rk_step(X, dt, steps)
+        op.sync()
+        return float(mismatch_loss(X, tgt, vol))
+
+    base = theta_of(c)
+
+    L0 = loss_at(base, U)
+    rows = []
+    for j in range(21):
+        h = 1e-6 * abs(float(base[j]))
+        tp, tm = base.clone(), base.clone()
+        tp[j] += h
+        tm[j] -= h
+        Lp, Lm = loss_at(tp, U), loss_at(tm, U)
+        rows.append((j, h, (Lp - Lm) / (2 * h), abs(Lp + Lm - 2 * L0)))
+    # rounding level of the loss values: the largest second difference over the
+    # coefficients bounds it (the curvature part h^2 L'' is far smaller)
+    sigma = max(r[3] for r in rows)
+    strict = 0
+    for j, h, fd, _ in rows:
+        ad = float(th.grad[j])
+        rel = abs(fd - ad) / max(abs(fd), 1e-300)
+        res = sigma / h
+        print(f"[fd] theta[{j}] fd {fd:.10e} adjoint {ad:.10e} rel {rel:.2e} "
+              f"fd-resolution {res:.1e}", flush=True)
+        if abs(ad) > 1e3 * res:          # resolved by the difference quotient
+            assert rel < 1e-6, j
+            strict += 1
+        else:
+            assert abs(fd - ad) < 4 * res, j
+    assert strict >= 4
+    g = torch.Generator(device="cpu").manual_seed(5)
+    for k in range(4):
+        v = torch.rand(U.shape, generator=g, dtype=torch.float64).to(DEV) * 2 - 1
+        eps = 1e-6
+        fd = (loss_at(base, U + eps * v) - loss_at(base, U - eps * v)) / (2 * eps)
+        ad = float((U0.grad * v).sum())
+        rel = abs(fd - ad) / abs(fd)
+        print(f"[fd] U0 direction {k}: fd {fd:.10e} adjoint {ad:.10e} rel {rel:.2e}", flush=True)
+        assert rel < 1e-6
+    op.set_coeffs(c)
