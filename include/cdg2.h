@@ -156,6 +156,36 @@ int cdg2_apply_adjoint(cdg2_handle* h, const void* U, const void* w, void* JTw, 
 int cdg2_rk_step_adjoint(cdg2_handle* h, const void* U_n, const void* lam_np1, void* lam_n, double dt,
                          double* dtheta_acc);
 
+/* ---- batched instances ---------------------------------------------------------
+ * Many independent 2D instances (own grid, order 1..3, coefficients; FP64) are
+ * advanced together: one persistent launch per SSP-RK3 stage walks a work list
+ * of (instance, block of cells) items in a schedule set by
+ * cdg2_batch_set_schedule; cdg2_batch_rk replays the stages of nsteps steps as
+ * one HIP graph.  The packed state holds instance i at element offset
+ * cdg2_batch_offset(b, i), each in the DOF layout above. */
+typedef struct cdg2_batch cdg2_batch;
+
+/* Copy count configs (2D, FP64, order <= 3; else CDG2_EINVAL), allocate the
+ * descriptor table, work list and two packed stage buffers (CDG2_ENOMEM). */
+int cdg2_batch_create(const cdg2_config* cfgs, int count, cdg2_batch** out);
+int cdg2_batch_destroy(cdg2_batch* b);
+int cdg2_batch_set_stream(cdg2_batch* b, void* hip_stream);
+/* Total entries of the packed state, and the element offset of instance i
+ * ((size_t)-1 if i is out of range). */
+size_t cdg2_batch_num_dofs(const cdg2_batch* b);
+size_t cdg2_batch_offset(const cdg2_batch* b, int i);
+/* Schedule: eb = cells per work item (16, 32 or 64; 6*eb threads per
+ * workgroup), nwg = persistent workgroups (0: one per item), order = 0 items
+ * sorted by decreasing cost, 1 in instance order.  Rebuilds the work list. */
+int cdg2_batch_set_schedule(cdg2_batch* b, int eb, int nwg, int order);
+/* nsteps SSP-RK3 steps of every instance, in place on the packed device buffer
+ * U_packed, instance i with time step dts[i] (HOST array of count doubles).
+ * use_graph != 0: the 3*nsteps launches are captured once per (U_packed,
+ * nsteps) into a HIP graph and replayed.  Asynchronous; see cdg2_batch_sync. */
+int cdg2_batch_rk(cdg2_batch* b, void* U_packed, const double* dts, int nsteps, int use_graph);
+/* Wait for the batch's stream; report non-finite / domain conditions. */
+int cdg2_batch_sync(cdg2_batch* b);
+
 /* Thread-local message of the last error. */
 const char* cdg2_last_error(void);
 

@@ -74,11 +74,23 @@ def lib():
     L.cdg2_rho_hat.restype = _d
     L.cdg2_apply_adjoint.argtypes = [P, P, P, P, ctypes.POINTER(_d)]
     L.cdg2_rk_step_adjoint.argtypes = [P, P, P, P, _d, ctypes.POINTER(_d)]
+    L.cdg2_batch_create.argtypes = [ctypes.POINTER(cdg2_config), ctypes.c_int, ctypes.POINTER(P)]
+    L.cdg2_batch_destroy.argtypes = [P]
+    L.cdg2_batch_set_stream.argtypes = [P, P]
+    L.cdg2_batch_num_dofs.argtypes = [P]
+    L.cdg2_batch_num_dofs.restype = ctypes.c_size_t
+    L.cdg2_batch_offset.argtypes = [P, ctypes.c_int]
+    L.cdg2_batch_offset.restype = ctypes.c_size_t
+    L.cdg2_batch_set_schedule.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.cdg2_batch_rk.argtypes = [P, P, ctypes.POINTER(_d), ctypes.c_int, ctypes.c_int]
+    L.cdg2_batch_sync.argtypes = [P]
     L.cdg2_last_error.argtypes = []
     L.cdg2_last_error.restype = ctypes.c_char_p
     for name in ("cdg2_create", "cdg2_destroy", "cdg2_set_stream", "cdg2_set_coeffs",
                  "cdg2_apply_operator", "cdg2_rk_step", "cdg2_max_dt", "cdg2_sync",
-                 "cdg2_apply_adjoint", "cdg2_rk_step_adjoint"):
+                 "cdg2_apply_adjoint", "cdg2_rk_step_adjoint", "cdg2_batch_create",
+                 "cdg2_batch_destroy", "cdg2_batch_set_stream", "cdg2_batch_set_schedule",
+                 "cdg2_batch_rk", "cdg2_batch_sync"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -173,6 +185,42 @@ def cdg2_rk_step_adjoint(h, Un_ptr: int, lam_np1_ptr: int, lam_n_ptr: int, dt: f
                                       ctypes.c_void_p(lam_n_ptr), float(dt), arr))
     if dtheta_acc is not None:
         dtheta_acc[:] = list(arr)
+
+
+def cdg2_batch_create(cfgs) -> ctypes.c_void_p:
+    arr = (cdg2_config * len(cfgs))(*cfgs)
+    h = ctypes.c_void_p()
+    _check(lib().cdg2_batch_create(arr, len(cfgs), ctypes.byref(h)))
+    return h
+
+
+def cdg2_batch_destroy(b) -> None:
+    _check(lib().cdg2_batch_destroy(b))
+
+
+def cdg2_batch_set_stream(b, stream: int) -> None:
+    _check(lib().cdg2_batch_set_stream(b, ctypes.c_void_p(stream)))
+
+
+def cdg2_batch_num_dofs(b) -> int:
+    return int(lib().cdg2_batch_num_dofs(b))
+
+
+def cdg2_batch_offset(b, i: int) -> int:
+    return int(lib().cdg2_batch_offset(b, int(i)))
+
+
+def cdg2_batch_set_schedule(b, eb: int, nwg: int, order: int) -> None:
+    _check(lib().cdg2_batch_set_schedule(b, int(eb), int(nwg), int(order)))
+
+
+def cdg2_batch_rk(b, U_ptr: int, dts, nsteps: int, use_graph: bool = True) -> None:
+    arr = (_d * len(dts))(*[float(x) for x in dts])
+    _check(lib().cdg2_batch_rk(b, ctypes.c_void_p(U_ptr), arr, int(nsteps), 1 if use_graph else 0))
+
+
+def cdg2_batch_sync(b) -> None:
+    _check(lib().cdg2_batch_sync(b))
 
 
 def cdg2_sync(h) -> None:

@@ -7,10 +7,13 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
+#include <algorithm>
 
 #include "../../include/cdg2.h"
 #include "cfl_kernel.hpp"
 #include "adj_kernel.hpp"
+#include "batch_kernel.hpp"
 #include "es_kernel.hpp"
 #include "tables.cpp"
 
@@ -434,5 +437,230 @@ int cdg2_sync(cdg2_handle* h) {
 }
 
 const char* cdg2_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ---- batched instances ------------------------------------------------------------
+
+extern "C" int cdg2_batch_destroy(cdg2_batch* b);
+
+struct cdg2_batch {
+  int count = 0;
+  std::vector<BatchInst> insts;
+  std::vector<size_t> ndof;
+  size_t total = 0;
+  BatchInst* d_insts = nullptr;
+  WorkItem* d_items = nullptr;
+  int nitems = 0;
+  double* S0 = nullptr;
+  double* S1 = nullptr;
+  int* flags = nullptr;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  int eb = 32, nwg = 0, order = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  void* g_U = nullptr;
+  int g_nsteps = -1;
+};
+
+namespace {
+
+void batch_free_graph(cdg2_batch* b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  b->g_U = nullptr;
+  b->g_nsteps = -1;
+}
+
+int batch_build_items(cdg2_batch* b) {
+  std::vector<WorkItem> items;
+  std::vector<double> cost;
+  for (int i = 0; i < b->count; ++i) {
+    const int E = b->insts[i].prm.g.E;
+    const int q = b->insts[i].p + 1;
+    for (int e0 = 0; e0 < E; e0 += b->eb) {
+      items.push_back({i, e0});
+      cost.push_back((double)q * q * q);
+    }
+  }
+  if (b->order == 0) {
+    std::vector<int> idx(items.size());
+    for (size_t k = 0; k < idx.size(); ++k) idx[k] = (int)k;
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::vector<WorkItem> sorted(items.size());
+    for (size_t k = 0; k < idx.size(); ++k) sorted[k] = items[idx[k]];
+    items.swap(sorted);
+  }
+  if (b->d_items) (void)hipFree(b->d_items);
+  b->d_items = nullptr;
+  if (hipMalloc((void**)&b->d_items, items.size() * sizeof(WorkItem)) != hipSuccess)
+    return fail(CDG2_ENOMEM, "hipMalloc of the work list failed");
+  if (hipMemcpy(b->d_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(CDG2_EHIP, "work list upload failed");
+  b->nitems = (int)items.size();
+  batch_free_graph(b);
+  return CDG2_OK;
+}
+
+template <int EB>
+hipError_t batch_launch_eb(cdg2_batch* b, hipStream_t st, double* U, int stage) {
+  int grid = b->nwg > 0 ? std::min(b->nwg, b->nitems) : b->nitems;
+  hipLaunchKernelGGL((batch_stage_kernel<double, EB>), dim3(grid), dim3(6 * EB), 0, st, b->d_insts, b->d_items,
+                     b->nitems, U, b->S0, b->S1, stage, b->flags);
+  return hipGetLastError();
+}
+
+hipError_t batch_launch(cdg2_batch* b, hipStream_t st, double* U, int stage) {
+  switch (b->eb) {
+    case 16: return batch_launch_eb<16>(b, st, U, stage);
+    case 64: return batch_launch_eb<64>(b, st, U, stage);
+    default: return batch_launch_eb<32>(b, st, U, stage);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int cdg2_batch_create(const cdg2_config* cfgs, int count, cdg2_batch** out) {
+  if (!out || !cfgs || count <= 0) return fail(CDG2_EINVAL, "bad arguments");
+  *out = nullptr;
+  for (int i = 0; i < count; ++i) {
+    int rc = validate(&cfgs[i]);
+    if (rc) return rc;
+    if (cfgs[i].dim != 2 || cfgs[i].order > 3 || cfgs[i].precision != CDG2_FP64)
+      return fail(CDG2_EINVAL, "batched instances must be 2D, FP64, order 1..3 (instance %d)", i);
+  }
+  cdg2_batch* b = new (std::nothrow) cdg2_batch();
+  if (!b) return fail(CDG2_ENOMEM, "host allocation failed");
+  b->count = count;
+  b->insts.resize(count);
+  b->ndof.resize(count);
+  size_t off = 0;
+  for (int i = 0; i < count; ++i) {
+    BatchInst& in = b->insts[i];
+    std::memset(&in, 0, sizeof(in));
+    build_tables(cfgs[i].order, &in.prm.tb);
+    build_geo(cfgs[i], &in.prm.g);
+    coef_from(cfgs[i].coeffs, &in.prm.cf);
+    in.p = cfgs[i].order;
+    in.off = off;
+    const size_t nd = 6 * (size_t)in.prm.g.E * (size_t)((in.p + 1) * (in.p + 1));
+    b->ndof[i] = nd;
+    off += nd;
+  }
+  b->total = off;
+  if (hipMalloc((void**)&b->d_insts, count * sizeof(BatchInst)) != hipSuccess ||
+      hipMalloc((void**)&b->S0, off * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&b->S1, off * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&b->flags, 64) != hipSuccess) {
+    cdg2_batch_destroy(b);
+    return fail(CDG2_ENOMEM, "hipMalloc for the batch failed");
+  }
+  if (hipMemset(b->flags, 0, 64) != hipSuccess ||
+      hipMemcpy(b->d_insts, b->insts.data(), count * sizeof(BatchInst), hipMemcpyHostToDevice) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+    cdg2_batch_destroy(b);
+    return fail(CDG2_EHIP, "batch initialisation failed");
+  }
+  int rc = batch_build_items(b);
+  if (rc) {
+    cdg2_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return CDG2_OK;
+}
+
+int cdg2_batch_destroy(cdg2_batch* b) {
+  if (!b) return CDG2_OK;
+  batch_free_graph(b);
+  if (b->d_insts) (void)hipFree(b->d_insts);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->S0) (void)hipFree(b->S0);
+  if (b->S1) (void)hipFree(b->S1);
+  if (b->flags) (void)hipFree(b->flags);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
+  return CDG2_OK;
+}
+
+int cdg2_batch_set_stream(cdg2_batch* b, void* s) {
+  if (!b) return fail(CDG2_EINVAL, "batch is NULL");
+  b->stream = (hipStream_t)s;
+  return CDG2_OK;
+}
+
+size_t cdg2_batch_num_dofs(const cdg2_batch* b) { return b ? b->total : 0; }
+
+size_t cdg2_batch_offset(const cdg2_batch* b, int i) {
+  if (!b || i < 0 || i >= b->count) return (size_t)-1;
+  return b->insts[i].off;
+}
+
+int cdg2_batch_set_schedule(cdg2_batch* b, int eb, int nwg, int order) {
+  if (!b) return fail(CDG2_EINVAL, "batch is NULL");
+  if (eb != 16 && eb != 32 && eb != 64) return fail(CDG2_EINVAL, "eb must be 16, 32 or 64");
+  if (nwg < 0 || (order != 0 && order != 1)) return fail(CDG2_EINVAL, "bad schedule");
+  b->eb = eb;
+  b->nwg = nwg;
+  b->order = order;
+  return batch_build_items(b);
+}
+
+int cdg2_batch_rk(cdg2_batch* b, void* U_packed, const double* dts, int nsteps, int use_graph) {
+  if (!b || !U_packed || !dts) return fail(CDG2_EINVAL, "NULL argument");
+  if (nsteps < 0) return fail(CDG2_EINVAL, "nsteps < 0");
+  if (overlap(U_packed, b->S0, b->total * 8) || overlap(U_packed, b->S1, b->total * 8))
+    return fail(CDG2_EINVAL, "U_packed overlaps a stage buffer");
+  bool changed = false;
+  for (int i = 0; i < b->count; ++i) {
+    if (!std::isfinite(dts[i])) return fail(CDG2_EINVAL, "dt of instance %d is not finite", i);
+    if (b->insts[i].dt != dts[i]) changed = true;
+    b->insts[i].dt = dts[i];
+  }
+  if (changed)
+    HIP_TRY(hipMemcpyAsync(b->d_insts, b->insts.data(), b->count * sizeof(BatchInst), hipMemcpyHostToDevice,
+                           b->stream));
+  double* U = (double*)U_packed;
+  if (!use_graph || nsteps == 0) {
+    for (int n = 0; n < nsteps; ++n)
+      for (int st = 1; st <= 3; ++st) HIP_TRY(batch_launch(b, b->stream, U, st));
+    return CDG2_OK;
+  }
+  if (!b->gexec || b->g_U != U_packed || b->g_nsteps != nsteps) {
+    batch_free_graph(b);
+    HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int n = 0; n < nsteps && e == hipSuccess; ++n)
+      for (int st = 1; st <= 3 && e == hipSuccess; ++st) e = batch_launch(b, b->cap, U, st);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(CDG2_EHIP, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+    b->g_U = U_packed;
+    b->g_nsteps = nsteps;
+  }
+  HIP_TRY(hipGraphLaunch(b->gexec, b->stream));
+  return CDG2_OK;
+}
+
+int cdg2_batch_sync(cdg2_batch* b) {
+  if (!b) return fail(CDG2_EINVAL, "batch is NULL");
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  int f = 0;
+  HIP_TRY(hipMemcpy(&f, b->flags, sizeof f, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemset(b->flags, 0, sizeof(int)));
+  if (f & FLAG_NONFINITE) return fail(CDG2_ENONFINITE, "non-finite value written to a state buffer");
+  if (f & FLAG_DOMAIN) return fail(CDG2_EDOMAIN, "c + chi^th <= 0 in a chemotactic sensitivity");
+  return CDG2_OK;
+}
 
 }  // extern "C"
