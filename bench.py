@@ -82,6 +82,113 @@ def cpu_baseline(dim, n, p, key, dof):
                       f"({dof} DOF) in {sec:.2f} s; GDOF/s = DOF / seconds"}
 
 
+def time_ms(fn, reps=1):
+    import torch
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def bench_batched(steps=50):
+    """256 independent 2D instances (grid side 32..128, order 1..3, coefficients
+    within +-50%): one persistent launch per stage, graph-replayed, autotuned,
+    against 256 sequential plain per-instance rk_step runs of the same instances."""
+    import torch
+
+    from paper_1403_1157_amd import inputs
+    from paper_1403_1157_amd.batch import Batch
+    from paper_1403_1157_amd.cdg2 import Operator
+
+    insts = inputs.batch_instances(256)
+    states, dts, ops = [], [], []
+    for it in insts:
+        U = torch.from_numpy(inputs.initial_modes(2, it["n"], it["order"], it["key"])).cuda()
+        op = Operator(2, it["n"], it["order"], it["coeffs"])
+        states.append(U)
+        dts.append(op.max_dt(U, 0.9))
+        ops.append(op)
+    dof = sum(U.numel() for U in states)
+    bt = Batch(insts)
+    packed = bt.pack(states)
+    tune = bt.autotune(packed, dts)
+    work = packed.clone()
+    bt.rk(work, dts, steps)          # capture + warm the graph
+    bt.sync()
+    ms_b = time_ms(lambda: bt.rk(work, dts, steps))
+    bt.sync()
+    plain = [U.clone() for U in states]
+
+    def run_plain():
+        for op, X, dt in zip(ops, plain, dts):
+            op.rk_step(X, dt, steps)
+
+    run_plain()
+    ms_p = time_ms(run_plain)
+    for op in ops:
+        op.sync()
+        op.close()
+    bt.close()
+    return {"instances": 256, "steps": steps, "dof": dof, "schedule": tune["schedule"],
+            "ms_batched": round(ms_b, 3), "ms_plain_sequential": round(ms_p, 3),
+            "speedup_vs_plain": round(ms_p / ms_b, 3),
+            "gdof_steps_per_s_batched": round(dof * steps / (ms_b * 1e-3) / 1e9, 3),
+            "gdof_steps_per_s_plain": round(dof * steps / (ms_p * 1e-3) / 1e9, 3)}
+
+
+def bench_adjoint(steps=200, ckpt=20):
+    """128^2 Q2, 200 SSP-RK3 steps, checkpoints every 20: forward time, forward +
+    gradient (loss: L2 mismatch of final n1 and c3 against a target run with the
+    21 coefficients perturbed by 10%), and one J^T w apply against one f apply."""
+    import torch
+
+    from paper_1403_1157_amd import inputs
+    from paper_1403_1157_amd.autograd import CDG2RK, mismatch_loss, theta_of
+    from paper_1403_1157_amd.cdg2 import Operator
+
+    n = (128, 128)
+    c = inputs.adjoint_coeffs()
+    U0 = torch.from_numpy(inputs.initial_modes(2, n, 2, (4,))).cuda()
+    op = Operator(2, n, 2, c)
+    dt = op.max_dt(U0, 0.9)
+    tgt = U0.clone()
+    opt = Operator(2, n, 2, inputs.adjoint_target_coeffs())
+    opt.rk_step(tgt, dt, steps)
+    opt.sync()
+    vol = 1.0 / (n[0] * n[1])
+
+    def fwd():
+        X = U0.clone()
+        op.rk_step(X, dt, steps)
+
+    def fwd_bwd():
+        X = U0.clone().requires_grad_(True)
+        th = theta_of(c).requires_grad_(True)
+        L = mismatch_loss(CDG2RK.apply(X, th, op, c, dt, steps, ckpt), tgt, vol)
+        L.backward()
+
+    fwd()
+    ms_f = time_ms(fwd)
+    fwd_bwd()
+    ms_fb = time_ms(fwd_bwd)
+    w = torch.randn_like(U0)
+    out = torch.empty_like(U0)
+    op.apply(U0, out)
+    op.apply_adjoint(U0, w, out)
+    us_a = time_ms(lambda: op.apply(U0, out), 20) * 1e3
+    us_t = time_ms(lambda: op.apply_adjoint(U0, w, out), 20) * 1e3
+    op.sync()
+    return {"workload": "128x128 Q2, 200 SSP-RK3 steps, checkpoint every 20, 21 coefficients + U0",
+            "ms_forward": round(ms_f, 3), "ms_forward_and_gradient": round(ms_fb, 3),
+            "gradient_over_forward": round(ms_fb / ms_f, 3),
+            "us_apply": round(us_a, 2), "us_apply_adjoint": round(us_t, 2),
+            "adjoint_over_apply": round(us_t / us_a, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +196,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="3d-q2-64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched and adjoint measurements")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM "
                          "byte counters of a profiler run) and exit")
@@ -176,6 +285,9 @@ def main():
                   "gdof_s": round(dof / (ms_apply * 1e-3) / 1e9, 4),
                   "alg_gb_s": round(16.0 * dof / (ms_apply * 1e-3) / 1e9, 2)},
     }
+    if not args.no_extras:
+        line["batched"] = bench_batched()
+        line["adjoint"] = bench_adjoint()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(dim, n, p, key, dof)
     print(json.dumps(line), flush=True)
