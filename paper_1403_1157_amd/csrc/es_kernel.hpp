@@ -1,8 +1,22 @@
 // CDG2 operator kernel, one thread per (cell, species).
 //
-// Same discrete operator as described in op_kernel.hpp (Section 3.1 volume and
-// face integrals, LLF convective flux, CDG2 lifting on K^-, M^{-1} = 1/|K|,
-// optional SSP-RK3 stage combination in the epilogue).  Mapping:
+// Per cell (Section 3.1) the residual is
+//   volume:   int_K (F(U) - A grad U) : grad phi + S(U) phi
+//   faces:    int_e {A grad phi}:[[U]] + {A grad U}:[[phi]] - (F^ - A^):[[phi]]
+// with the local Lax-Friedrichs flux F^ and the CDG2 flux
+// A^ = 2 chi_e (A r_e([[U]]))|_{K^-_e}.  On Cartesian cells with the orthonormal
+// Legendre basis the lifting of a face jump on K^- (the low-side cell) has the
+// trace -(liftc / (2h)) [[U]], liftc = sum_i phi_i(1)^2, so A^ . n^- is
+// -chi_e a liftc / h (u^- - u^+): it is formed from K^-'s end values only.
+// Each cell evaluates all of its faces from its own side, in its outward normal
+// n_o (the expression is symmetric in the two sides):
+//   R_j += int_e 1/2 a (u_o - u_n) d_{n_o} phi_j
+//        + [ 1/2 a (d_{n_o} u_o + d_{n_o} u_n) - pen (u_o - u_n)
+//            - 1/2 (F_o + F_n).n_o - 1/2 lam (u_o - u_n) ] phi_j,
+// then f = R / |K| (M = |K| I), optionally combined with an SSP-RK3 stage in the
+// epilogue so that f never reaches HBM.
+//
+// Mapping:
 //   * a workgroup owns EB consecutive cells; thread (s, el) keeps the modes and
 //     the modal residual of species s of cell el in registers;
 //   * everything linear in U is applied by that thread alone, exactly, in modal
@@ -15,7 +29,6 @@
 //     last axis) at a time, the faces one face direction at a time.  Point items
 //     (cell, point) evaluate w1, w2, F1, F2, alpha n c, lambda and the inflow
 //     fluxes; species threads integrate them back against their test functions.
-// Each face is evaluated from both sides (every cell treats all its faces).
 #pragma once
 
 #include "op_common.hpp"
