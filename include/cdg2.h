@@ -150,9 +150,9 @@ int cdg2_apply_adjoint(cdg2_handle* h, const void* U, const void* w, void* JTw, 
  *   lam2 = 2/3 lam3 + 2/3 dt J(U2)^T lam3,  lam1 = 1/4 lam2 + 1/4 dt J(U1)^T lam2,
  *   lam_n = 1/3 lam3 + 3/4 lam2 + lam1 + dt J(U_n)^T lam1,
  * with U1, U2 recomputed from U_n into the stage buffers.  lam_n may alias
- * lam_np1 (in place) but not U_n.  If dtheta_acc (HOST, CDG2_NDIFF doubles) is
- * not NULL, 2/3 dt df(U2)/dtheta^T lam3 + 1/4 dt df(U1)/dtheta^T lam2 +
- * dt df(U_n)/dtheta^T lam1 is ADDED to it and the call waits for the device. */
+ * lam_np1 (in place) but not U_n.  If dtheta_acc (a DEVICE array of CDG2_NDIFF
+ * doubles) is not NULL, 2/3 dt df(U2)/dtheta^T lam3 + 1/4 dt df(U1)/dtheta^T lam2
+ * + dt df(U_n)/dtheta^T lam1 is ADDED to it in stream order (no host wait). */
 int cdg2_rk_step_adjoint(cdg2_handle* h, const void* U_n, const void* lam_np1, void* lam_n, double dt,
                          double* dtheta_acc);
 

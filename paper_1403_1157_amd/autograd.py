@@ -11,7 +11,6 @@ library; this module only orders the calls and holds the checkpoints.
 """
 from __future__ import annotations
 
-import numpy as np
 import torch
 
 from .cdg2 import COEFF_NAMES, Operator
@@ -56,7 +55,7 @@ class CDG2RK(torch.autograd.Function):
         op, dt, nsteps, ckpt = ctx.op, ctx.dt, ctx.nsteps, ctx.ckpt
         op.set_coeffs(coeffs_with(ctx.base, ctx.theta))
         lam = gU.detach().contiguous().clone()
-        dth = np.zeros(NDIFF)
+        dth = torch.zeros(NDIFF, dtype=torch.float64, device=lam.device)
         nseg = (nsteps + ckpt - 1) // ckpt
         for seg in reversed(range(nseg)):
             start = seg * ckpt
@@ -69,7 +68,7 @@ class CDG2RK(torch.autograd.Function):
             for n in reversed(range(start, end)):
                 op.rk_step_adjoint(states[n - start], lam, lam, dt, dth)
         op.sync()
-        return lam, torch.from_numpy(dth), None, None, None, None, None
+        return lam, dth.cpu(), None, None, None, None, None
 
 
 def mismatch_loss(U: torch.Tensor, target: torch.Tensor, vol: float, species=(0, 5)) -> torch.Tensor:

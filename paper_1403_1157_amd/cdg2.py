@@ -176,15 +176,13 @@ def cdg2_apply_adjoint(h, U_ptr: int, w_ptr: int, out_ptr: int, want_theta: bool
     return list(arr) if want_theta else None
 
 
-def cdg2_rk_step_adjoint(h, Un_ptr: int, lam_np1_ptr: int, lam_n_ptr: int, dt: float, dtheta_acc=None):
-    """dtheta_acc: None or a numpy float64 array of 21 entries, added to in place."""
-    arr = None
-    if dtheta_acc is not None:
-        arr = (_d * 21)(*[float(x) for x in dtheta_acc])
+def cdg2_rk_step_adjoint(h, Un_ptr: int, lam_np1_ptr: int, lam_n_ptr: int, dt: float,
+                         dtheta_acc_ptr: int = 0):
+    """dtheta_acc_ptr: 0 or the device address of 21 float64 accumulators."""
     _check(lib().cdg2_rk_step_adjoint(h, ctypes.c_void_p(Un_ptr), ctypes.c_void_p(lam_np1_ptr),
-                                      ctypes.c_void_p(lam_n_ptr), float(dt), arr))
-    if dtheta_acc is not None:
-        dtheta_acc[:] = list(arr)
+                                      ctypes.c_void_p(lam_n_ptr), float(dt),
+                                      ctypes.cast(ctypes.c_void_p(dtheta_acc_ptr or None),
+                                                  ctypes.POINTER(_d))))
 
 
 def cdg2_batch_create(cfgs) -> ctypes.c_void_p:
@@ -284,8 +282,15 @@ class Operator:
         return (out, th) if want_theta else out
 
     def rk_step_adjoint(self, U_n, lam_np1, lam_n, dt, dtheta_acc=None):
+        """dtheta_acc: None or a CUDA float64 tensor of 21 entries, added to in place."""
         self._stream()
-        cdg2_rk_step_adjoint(self.h, self._arg(U_n), self._arg(lam_np1), self._arg(lam_n), dt, dtheta_acc)
+        ptr = 0
+        if dtheta_acc is not None:
+            if not (dtheta_acc.is_cuda and dtheta_acc.dtype == torch.float64
+                    and dtheta_acc.is_contiguous() and dtheta_acc.numel() == 21):
+                raise ValueError("dtheta_acc must be a contiguous CUDA float64 tensor of 21 entries")
+            ptr = dtheta_acc.data_ptr()
+        cdg2_rk_step_adjoint(self.h, self._arg(U_n), self._arg(lam_np1), self._arg(lam_n), dt, ptr)
         return lam_n
 
     def set_coeffs(self, coeffs: dict) -> None:

@@ -117,17 +117,10 @@ void build_geo(const cdg2_config& c, Geo* g) {
 
 // ---- launch dispatch ----------------------------------------------------------
 
-template <int D, int P>
-struct LaunchCfg {
-  // cells per workgroup and workgroup size
-  static constexpr int EPW = D == 3 ? 1 : (P <= 2 ? 4 : 2);
-  static constexpr int NT = D == 3 ? 64 : 128;
-};
-
 // cells per workgroup of the (cell, species) kernel: 6 * EB threads
 template <int D, int P>
 struct EsCfg {
-  static constexpr int EB = D == 3 ? 32 : 32;
+  static constexpr int EB = D == 3 ? 10 : 32;
 };
 
 template <int D, int P, typename T>
@@ -142,10 +135,10 @@ hipError_t launch_op(cdg2_handle* h, const void* U, const void* U0, void* out, d
 
 template <int D, int P, typename T>
 hipError_t launch_cfl(cdg2_handle* h, const void* U) {
-  using L = LaunchCfg<D, P>;
-  int nb = (h->geo.E + L::EPW - 1) / L::EPW;
-  hipLaunchKernelGGL((cfl_kernel<D, P, T, L::EPW, L::NT>), dim3(nb), dim3(L::NT), 0, h->stream, h->dprm,
-                     (const T*)U, h->red, h->flags);
+  constexpr int EB = EsCfg<D, P>::EB;
+  int nb = (h->geo.E + EB - 1) / EB;
+  hipLaunchKernelGGL((cfl_kernel<D, P, T, EB>), dim3(nb), dim3(6 * EB), 0, h->stream, h->dprm, (const T*)U,
+                     h->red, h->flags);
   return hipGetLastError();
 }
 
@@ -381,23 +374,22 @@ int cdg2_rk_step_adjoint(cdg2_handle* h, const void* U_n, const void* lam_np1, v
   int rc = ensure_adjoint(h);
   if (rc) return rc;
   const int th = dtheta_acc != nullptr;
-  if (th) HIP_TRY(hipMemsetAsync(h->dth, 0, CDG2_NDIFF * sizeof(double), h->stream));
+  double* acc_save = h->dth;
+  if (th) h->dth = dtheta_acc;   // the reductions add straight into the caller's buffer
   // forward stages of the step, recomputed from U_n
-  HIP_TRY(run_op(h, U_n, nullptr, h->stage[0], dt, 0.0, 1.0, 1));
-  HIP_TRY(run_op(h, h->stage[0], U_n, h->stage[1], dt, 0.75, 0.25, 2));
+  hipError_t e = run_op(h, U_n, nullptr, h->stage[0], dt, 0.0, 1.0, 1);
+  if (e == hipSuccess) e = run_op(h, h->stage[0], U_n, h->stage[1], dt, 0.75, 0.25, 2);
   // reverse sweep of the Shu-Osher stages
   //   lam2 = 2/3 lam3 + 2/3 dt J(U2)^T lam3
   //   lam1 = 1/4 lam2 + 1/4 dt J(U1)^T lam2
   //   lam_n = 1/3 lam3 + 3/4 lam2 + lam1 + dt J(U_n)^T lam1
-  HIP_TRY(run_adj(h, h->stage[1], lam_np1, h->adj[0], 2.0 / 3.0, 2.0 / 3.0 * dt, nullptr, 0.0, nullptr, 0.0, th));
-  HIP_TRY(run_adj(h, h->stage[0], h->adj[0], h->adj[1], 0.25, 0.25 * dt, nullptr, 0.0, nullptr, 0.0, th));
-  HIP_TRY(run_adj(h, U_n, h->adj[1], lam_n, 1.0, dt, lam_np1, 1.0 / 3.0, h->adj[0], 0.75, th));
-  if (th) {
-    double tmp[CDG2_NDIFF];
-    HIP_TRY(hipMemcpyAsync(tmp, h->dth, sizeof tmp, hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    for (int j = 0; j < CDG2_NDIFF; ++j) dtheta_acc[j] += tmp[j];
-  }
+  if (e == hipSuccess)
+    e = run_adj(h, h->stage[1], lam_np1, h->adj[0], 2.0 / 3.0, 2.0 / 3.0 * dt, nullptr, 0.0, nullptr, 0.0, th);
+  if (e == hipSuccess)
+    e = run_adj(h, h->stage[0], h->adj[0], h->adj[1], 0.25, 0.25 * dt, nullptr, 0.0, nullptr, 0.0, th);
+  if (e == hipSuccess) e = run_adj(h, U_n, h->adj[1], lam_n, 1.0, dt, lam_np1, 1.0 / 3.0, h->adj[0], 0.75, th);
+  h->dth = acc_save;
+  if (e != hipSuccess) return fail(CDG2_EHIP, "adjoint step launch: %s", hipGetErrorString(e));
   return CDG2_OK;
 }
 

@@ -73,6 +73,54 @@ __device__ __forceinline__ void tapply_lo(const T* in, T* out, const double (*M0
   }
 }
 
+// Values (slot vslot) and, if gslot >= 0, physical gradients (slots gslot..+D-1)
+// of one species at the Gauss points of layer lc (along the last axis) of a cell,
+// from its modes u; out is the cell's [NVQ][NF] slot array.
+template <int D, int Q, typename T>
+__device__ __forceinline__ void produce_layer(const Tables& tb, const Geo& g, const T* u, int lc, T* out,
+                                              int vslot, int gslot) {
+  constexpr int NF = ipow(Q, D - 1), LST = NF, LA = D - 1;
+  const double(*Bt0)[CDG2_MAXQ] = tb.B;
+  T tv[NF], td[NF], o[NF];
+#pragma unroll
+  for (int r = 0; r < NF; ++r) {
+    T a0 = T(0), a1 = T(0);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      a0 += T(tb.B[lc][k]) * u[r + LST * k];
+      a1 += T(tb.Bd[lc][k]) * u[r + LST * k];
+    }
+    tv[r] = a0;
+    td[r] = a1;
+  }
+  tapply_lo<D, Q, false, T>(tv, o, Bt0, Bt0);
+#pragma unroll
+  for (int q = 0; q < NF; ++q) out[vslot * NF + q] = o[q];
+  if (gslot >= 0) {
+#pragma unroll
+    for (int a = 0; a < D - 1; ++a) {
+      tapply_lo<D, Q, false, T>(tv, o, a == 0 ? tb.Bd : tb.B, a == 1 ? tb.Bd : tb.B);
+#pragma unroll
+      for (int q = 0; q < NF; ++q) out[(gslot + a) * NF + q] = o[q] * T(g.ih[a]);
+    }
+    tapply_lo<D, Q, false, T>(td, o, Bt0, Bt0);
+#pragma unroll
+    for (int q = 0; q < NF; ++q) out[(gslot + LA) * NF + q] = o[q] * T(g.ih[LA]);
+  }
+}
+
+// Reciprocals of four positive numbers with one division: 1/a = (b c d) / (a b c d).
+template <typename T>
+__device__ __forceinline__ void recip4(T a, T b, T c, T d, T& ra, T& rb, T& rc, T& rd) {
+  const T ab = a * b, cd = c * d;
+  const T r = T(1) / (ab * cd);
+  const T rab = r * cd, rcd = r * ab;
+  ra = rab * b;
+  rb = rab * a;
+  rc = rcd * d;
+  rd = rcd * c;
+}
+
 template <int D, int P, typename T, int EB>
 __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict__ U, const T* U0, T* out,
                                          T dt, T ca, T cb, int stage, int* __restrict__ flags, int e0,
@@ -157,35 +205,7 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
   const double(*Bt0)[CDG2_MAXQ] = tb.B;
   for (int lc = 0; lc < Q; ++lc) {
     __syncthreads();
-    if (prod >= 0) {
-      // contract the layer axis with row lc of B (values, in-layer derivatives) and Bd
-      T tv[NF], td[NF], o[NF];
-#pragma unroll
-      for (int r = 0; r < NF; ++r) {
-        T a0 = T(0), a1 = T(0);
-#pragma unroll
-        for (int k = 0; k < Q; ++k) {
-          a0 += T(tb.B[lc][k]) * u[r + LST * k];
-          a1 += T(tb.Bd[lc][k]) * u[r + LST * k];
-        }
-        tv[r] = a0;
-        td[r] = a1;
-      }
-      tapply_lo<D, Q, false, T>(tv, o, Bt0, Bt0);
-#pragma unroll
-      for (int q = 0; q < PC; ++q) V[(el * NVQ + prod) * PC + q] = o[q];
-      if (grads) {
-#pragma unroll
-        for (int a = 0; a < D - 1; ++a) {
-          tapply_lo<D, Q, false, T>(tv, o, a == 0 ? tb.Bd : tb.B, a == 1 ? tb.Bd : tb.B);
-#pragma unroll
-          for (int q = 0; q < PC; ++q) V[(el * NVQ + gslot + a) * PC + q] = o[q] * T(g.ih[a]);
-        }
-        tapply_lo<D, Q, false, T>(td, o, Bt0, Bt0);
-#pragma unroll
-        for (int q = 0; q < PC; ++q) V[(el * NVQ + gslot + LA) * PC + q] = o[q] * T(g.ih[LA]);
-      }
-    }
+    if (prod >= 0) produce_layer<D, Q, T>(tb, g, u, lc, V + el * NVQ * PC, prod, grads ? gslot : -1);
     __syncthreads();
     // point pass: chemotactic fluxes and the alpha reaction term, weighted
     for (int it = tid; it < EB * PC; it += NT) {
@@ -195,8 +215,10 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
       const T d11 = c1 + T(c[K_XT11]), d13 = c3 + T(c[K_XT13]), d21 = c1 + T(c[K_XT21]),
               d22 = n1 + T(c[K_XT22]);
       if (e0 + l < E && !(d11 > T(0) && d13 > T(0) && d21 > T(0) && d22 > T(0))) flag |= FLAG_DOMAIN;
-      const T k11 = T(c[K_X011]) / d11, k13 = T(c[K_X013]) / d13, k21 = T(c[K_X021]) / d21,
-              k22 = T(c[K_X022]) / d22;
+      T r11, r13, r21, r22;
+      recip4(d11, d13, d21, d22, r11, r13, r21, r22);
+      const T k11 = T(c[K_X011]) * r11, k13 = T(c[K_X013]) * r13, k21 = T(c[K_X021]) * r21,
+              k22 = T(c[K_X022]) * r22;
       // weight of the point: |K| w_q (layer index lc along the last axis)
       T wt = vol * T(tb.w[lc]);
       if constexpr (D == 2) {
@@ -352,10 +374,13 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
         if (e0 + l < E && !(d11o > T(0) && d13o > T(0) && d21o > T(0) && d22o > T(0) &&
                             d11n > T(0) && d13n > T(0) && d21n > T(0) && d22n > T(0)))
           flag |= FLAG_DOMAIN;
-        const T w1o = so * (T(c[K_X011]) * dc1o / d11o + T(c[K_X013]) * dc3o / d13o);
-        const T w2o = so * (T(c[K_X021]) * dc1o / d21o - T(c[K_X022]) * dn1o / d22o);
-        const T w1n = so * (T(c[K_X011]) * dc1n / d11n + T(c[K_X013]) * dc3n / d13n);
-        const T w2n = so * (T(c[K_X021]) * dc1n / d21n - T(c[K_X022]) * dn1n / d22n);
+        T r11o, r13o, r21o, r22o, r11n, r13n, r21n, r22n;
+        recip4(d11o, d13o, d21o, d22o, r11o, r13o, r21o, r22o);
+        recip4(d11n, d13n, d21n, d22n, r11n, r13n, r21n, r22n);
+        const T w1o = so * (T(c[K_X011]) * dc1o * r11o + T(c[K_X013]) * dc3o * r13o);
+        const T w2o = so * (T(c[K_X021]) * dc1o * r21o - T(c[K_X022]) * dn1o * r22o);
+        const T w1n = so * (T(c[K_X011]) * dc1n * r11n + T(c[K_X013]) * dc3n * r13n);
+        const T w2n = so * (T(c[K_X021]) * dc1n * r21n - T(c[K_X022]) * dn1n * r22n);
         const T lam = fmax(fmax(fabs(w1o), fabs(w2o)), fmax(fabs(w1n), fabs(w2n)));
         x[0] = T(0.5) * lam;
         x[NF] = -T(0.5) * (n1o * w1o + n1n * w1n);

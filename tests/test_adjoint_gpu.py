@@ -73,11 +73,11 @@ def test_rk_step_adjoint_parity(dim, n, p):
     (o.rk_step(X, dt, 1, theta=th) * lam).sum().backward()
     op = gpu_op(cfg)
     lam_d = lam.to(DEV)
-    dth = np.zeros(21)
+    dth = torch.zeros(21, dtype=torch.float64, device=DEV)
     op.rk_step_adjoint(U.to(DEV), lam_d, lam_d, dt, dth)     # in place
     op.sync()
     assert_close(lam_d, X.grad, TOL["fp64"], "RK step adjoint")
-    theta_close(dth, th.grad[:21].numpy(), 1e-11)
+    theta_close(dth.cpu().numpy(), th.grad[:21].numpy(), 1e-11)
 
 
 def test_checkpointed_gradient_matches_oracle():
