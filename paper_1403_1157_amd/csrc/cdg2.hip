@@ -113,6 +113,7 @@ void build_geo(const cdg2_config& c, Geo* g) {
   g->g1in[0] = c.gamma1_in[0];
   g->g1in[1] = c.gamma1_in[1];
   g->chi_e = 0.5 * (2 * c.dim);  // N/2, N = 2d faces per cell
+  g->tz = c.dim == 3 ? 8 : 0;   // slabs of 8 z-planes (processing order of the 3D kernel)
 }
 
 // ---- launch dispatch ----------------------------------------------------------

@@ -134,8 +134,8 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
   const int tid = threadIdx.x;
   const int s = tid / EB, el = tid % EB;
   const int E = g.E;
-  const int e = e0 + el;
-  const bool live = e < E;
+  const bool live = e0 + el < E;
+  const int e = live ? cell_of<D>(g, e0 + el) : 0;
   const size_t SE = (size_t)E * NM;
   const T vol = T(g.vol);
   int flag = 0;
@@ -143,13 +143,13 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
   // ---- own modes, neighbour table ------------------------------------------------
   T u[NM], R[NM];
   {
-    const T* src = U + s * SE + (size_t)(live ? e : 0) * NM;
+    const T* src = U + s * SE + (size_t)e * NM;
 #pragma unroll
     for (int m = 0; m < NM; ++m) u[m] = live ? src[m] : T(0);
   }
   for (int it = tid; it < EB * NFACE; it += NT) {
     int l = it / NFACE, f = it % NFACE;
-    sm.nb[l][f] = e0 + l < E ? neighbour<D>(g, e0 + l, f) : -3;
+    sm.nb[l][f] = e0 + l < E ? neighbour<D>(g, cell_of<D>(g, e0 + l), f) : -3;
   }
 
   // ---- linear volume terms: -a_s |K| sum_a h_a^-2 (S along a) u + linear reactions --
@@ -173,7 +173,7 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
     // S_lin: n1: -d1 n1; n2: -d2 n2; n3: (d1 - gamma) n1 + d2 n2; c1: f1 n3;
     //        c2: -k c2; c3: k c2.  Other species' modes of the same cell come from
     //        global memory (the workgroup has just read them).
-    const T* cell = U + (size_t)(live ? e : 0) * NM;
+    const T* cell = U + (size_t)e * NM;
     if (s == S_N1 || s == S_N2 || s == S_C2) {
       const T k = -T(s == S_N1 ? c[K_D1] : s == S_N2 ? c[K_D2] : c[K_K]) * vol;
 #pragma unroll
@@ -390,7 +390,7 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
         if (nbl == -1) {
           if (c1o - T(c[K_C1S]) > T(0)) q1 = T(c[K_MU1] * c[K_BE1]);
           const int tb0 = t % Q;
-          const double xc = (cell_coord<D>(g, e0 + l, b0) + tb.x[tb0]) * g.h[b0];
+          const double xc = (cell_coord<D>(g, cell_of<D>(g, e0 + l), b0) + tb.x[tb0]) * g.h[b0];
           if (xc >= g.g1in[0] && xc <= g.g1in[1]) q5 = T(c[K_NU2] * c[K_SIG]);
         } else if (nbl == -2) {
           if (c1o - T(c[K_C1SS]) > T(0)) q2 = T(c[K_MU2] * c[K_BE2]);

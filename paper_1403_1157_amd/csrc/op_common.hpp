@@ -29,7 +29,7 @@ struct Geo {
   int E;             // number of cells
   int wall;          // wall axis (-1: fully periodic)
   int llf_cells;     // 1: LLF dissipation on n1, n2 only
-  int pad;
+  int tz;            // z-planes per slab of the processing order (<= 1: lexicographic)
   double h[3], ih[3];
   double vol;        // |K|
   double area[3];    // |e| of a face normal to each axis
@@ -178,6 +178,23 @@ __device__ __forceinline__ int neighbour(const Geo& g, int e, int f) {
   }
   c[a] = v;
   return c[0] + g.n[0] * (c[1] + g.n[1] * c[2]);
+}
+
+// Cell at position i of the processing order.  The x index runs fastest, so
+// EB consecutive positions are (mostly) EB consecutive cells of one row; the rows
+// (y, z) are visited in slabs of tz z-planes, y outer and z inner within a slab.
+// The y- and z-neighbours of a row were then read at most 2 tz rows earlier,
+// while the state is still in the L2 cache of the XCD, instead of one whole
+// z-plane earlier as in the lexicographic order.
+template <int D>
+__device__ __forceinline__ int cell_of(const Geo& g, int i) {
+  if (D == 2 || g.tz <= 1) return i;
+  const int nx = g.n[0], ny = g.n[1];
+  const int x = i % nx, r = i / nx;
+  const int slab = g.tz * ny;
+  const int z0 = (r / slab) * g.tz, w = r % slab;
+  const int tz = min(g.tz, g.n[2] - z0);
+  return x + nx * (w / tz + ny * (z0 + w % tz));
 }
 
 // Cell coordinate along axis a.
