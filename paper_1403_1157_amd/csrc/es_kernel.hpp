@@ -45,16 +45,82 @@ struct EsSz {
   static constexpr int NFQ = 14;           // face exchange: 4 values x 2 sides, 3 d_n x 2 sides
 };
 
-// LDS: one union buffer, reused by the volume layers and by the faces.
+// LDS: one union buffer, reused by the volume layers and by the faces, and in 3D
+// also as the staging area of coalesced loads and stores of whole cells' modes.
+// Staged loads move chunks of CB bytes (16, or 12 when a cell's modes are not a
+// multiple of 16 bytes), NCH per (cell, species); the load-to-LDS instruction
+// places lane t's chunk at 16 t bytes for both sizes, so chunk k of thread
+// g = (s, l) sits at byte 16 (g NCH + k) (a 12-byte chunk leaves 4 bytes unused).
 template <int D, int P, typename T, int EB>
 struct EsSmem {
   using S = EsSz<D, P>;
+  static constexpr bool STAGED = D == 3;
+  static constexpr int BYTES = S::NM * (int)sizeof(T);
+  static constexpr int CB = BYTES % 16 == 0 ? 16 : 12;
+  static constexpr int NCH = BYTES / CB;
   static constexpr int VOL = EB * S::NVQ * S::PC;
   static constexpr int FAC = EB * S::NFQ * S::NF;
-  static constexpr int N = VOL > FAC ? VOL : FAC;
-  T buf[N];
+  static constexpr int STG = STAGED ? 6 * EB * NCH * 16 / (int)sizeof(T) : 0;
+  static constexpr int N0 = VOL > FAC ? VOL : FAC;
+  static constexpr int N = N0 > STG ? N0 : STG;
   int nb[EB][2 * D];
+  int cell[EB];
+  __align__(16) T buf[N];
 };
+
+// Element m of thread g's staged modes.
+template <int D, int P, typename T, int EB>
+__device__ __forceinline__ T staged(const EsSmem<D, P, T, EB>& sm, int g, int m) {
+  using SM = EsSmem<D, P, T, EB>;
+  constexpr int CB = SM::CB, NCH = SM::NCH;
+  const int b = m * (int)sizeof(T), j = b / CB, r = b % CB;
+  const unsigned char* base = reinterpret_cast<const unsigned char*>(sm.buf);
+  if (r + (int)sizeof(T) <= CB) {
+    return *reinterpret_cast<const T*>(base + (g * NCH + j) * 16 + r);
+  } else {   // a double split over two chunks, 4 + 4 bytes
+    const int lo = *reinterpret_cast<const int*>(base + (g * NCH + j) * 16 + r);
+    const int hi = *reinterpret_cast<const int*>(base + (g * NCH + j + 1) * 16);
+    return T(__hiloint2double(hi, lo));
+  }
+}
+
+// Start loading the modes of the cells idx[l * istride] (l < EB; outside [0, E):
+// none, cell 0 is loaded and not used) of all six species straight into the
+// staging area, without registers in flight: consecutive lanes take consecutive
+// chunks, so each load instruction reads whole cache lines of consecutive cells.
+// The caller waits (vmcnt) and synchronises before reading.
+template <int D, int P, typename T, int EB>
+__device__ __forceinline__ void stage_modes(const T* U, size_t SE, int E, EsSmem<D, P, T, EB>& sm,
+                                            const int* idx, int istride, int tid) {
+  using SM = EsSmem<D, P, T, EB>;
+  constexpr int NM = EsSz<D, P>::NM, NT = 6 * EB, CB = SM::CB, NCH = SM::NCH;
+  static_assert(SM::BYTES % CB == 0, "chunking");
+  constexpr int PER = EB * NCH;                 // chunks per species
+  constexpr int RR = (PER + NT - 1) / NT;
+  unsigned char* base = reinterpret_cast<unsigned char*>(sm.buf);
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // earlier LDS reads of the area are done
+#pragma unroll
+  for (int r = 0; r < RR; ++r) {
+    const int ch = r * NT + tid;
+    if (ch < PER) {
+      const int l = ch / NCH, k = ch % NCH;
+      const int n = idx[l * istride];
+      const char* src = reinterpret_cast<const char*>(U + (size_t)(n >= 0 && n < E ? n : 0) * NM) + k * CB;
+#pragma unroll
+      for (int sp = 0; sp < 6; ++sp) {
+        auto* dst = (__attribute__((address_space(3))) void*)(base + (sp * PER + r * NT) * 16);
+        const char* sps = src + (size_t)sp * SE * sizeof(T);
+        if constexpr (CB == 16) {
+          __builtin_amdgcn_global_load_lds(sps, dst, 16, 0, 0);
+        } else {
+          __builtin_amdgcn_global_load_lds(sps, dst, 12, 0, 0);
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void wait_staged() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // (D-1)-dimensional tensor contraction of NF values (tangential / layer axes).
 template <int D, int Q, bool TR, typename T>
@@ -141,15 +207,24 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
   int flag = 0;
 
   // ---- own modes, neighbour table ------------------------------------------------
+  constexpr bool STAGED = EsSmem<D, P, T, EB>::STAGED;
   T u[NM], R[NM];
-  {
-    const T* src = U + s * SE + (size_t)e * NM;
-#pragma unroll
-    for (int m = 0; m < NM; ++m) u[m] = live ? src[m] : T(0);
-  }
   for (int it = tid; it < EB * NFACE; it += NT) {
     int l = it / NFACE, f = it % NFACE;
     sm.nb[l][f] = e0 + l < E ? neighbour<D>(g, cell_of<D>(g, e0 + l), f) : -3;
+  }
+  if constexpr (STAGED) {
+    if (tid < EB) sm.cell[tid] = e0 + tid < E ? cell_of<D>(g, e0 + tid) : -1;
+    __syncthreads();
+    stage_modes<D, P, T, EB>(U, SE, E, sm, sm.cell, 1, tid);
+    wait_staged();
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NM; ++m) u[m] = live ? staged<D, P, T, EB>(sm, tid, m) : T(0);
+  } else {
+    const T* src = U + s * SE + (size_t)e * NM;
+#pragma unroll
+    for (int m = 0; m < NM; ++m) u[m] = live ? src[m] : T(0);
   }
 
   // ---- linear volume terms: -a_s |K| sum_a h_a^-2 (S along a) u + linear reactions --
@@ -172,22 +247,23 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
     }
     // S_lin: n1: -d1 n1; n2: -d2 n2; n3: (d1 - gamma) n1 + d2 n2; c1: f1 n3;
     //        c2: -k c2; c3: k c2.  Other species' modes of the same cell come from
-    //        global memory (the workgroup has just read them).
+    //        the staging area (3D) or global memory (the workgroup has just read them).
     const T* cell = U + (size_t)e * NM;
     if (s == S_N1 || s == S_N2 || s == S_C2) {
       const T k = -T(s == S_N1 ? c[K_D1] : s == S_N2 ? c[K_D2] : c[K_K]) * vol;
 #pragma unroll
       for (int m = 0; m < NM; ++m) R[m] += k * u[m];
     } else if (live) {
-      const T* a0 = cell + (s == S_N3 ? S_N1 : s == S_C1 ? S_N3 : S_C2) * SE;
+      const int s0 = s == S_N3 ? S_N1 : s == S_C1 ? S_N3 : S_C2;
+      const T* a0 = cell + s0 * SE;
       const T k0 = T(s == S_N3 ? c[K_D1] - c[K_GAM] : s == S_C1 ? c[K_F1] : c[K_K]) * vol;
 #pragma unroll
-      for (int m = 0; m < NM; ++m) R[m] += k0 * a0[m];
+      for (int m = 0; m < NM; ++m) R[m] += k0 * (STAGED ? staged<D, P, T, EB>(sm, s0 * EB + el, m) : a0[m]);
       if (s == S_N3) {
         const T* a1 = cell + S_N2 * SE;
         const T k1 = T(c[K_D2]) * vol;
 #pragma unroll
-        for (int m = 0; m < NM; ++m) R[m] += k1 * a1[m];
+        for (int m = 0; m < NM; ++m) R[m] += k1 * (STAGED ? staged<D, P, T, EB>(sm, S_N2 * EB + el, m) : a1[m]);
       }
     }
   }
@@ -296,6 +372,9 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
   for (int sg = 0; sg < 2; ++sg) {
     const int f = 2 * a + sg;
     __syncthreads();
+    // 3D: the neighbours' modes arrive in the staging area while the own traces
+    // are formed
+    if constexpr (STAGED) stage_modes<D, P, T, EB>(U, SE, E, sm, &sm.nb[0][f], NFACE, tid);
     const int nb = sm.nb[el][f];
     // tangential-modal traces: value / d_a of own and neighbour, accurate jump
     T uo[NF], duo[NF], un[NF], dun[NF], jm[NF];
@@ -314,6 +393,10 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
       dun[J] = T(0);
       jm[J] = T(0);
     }
+    if constexpr (STAGED) {
+      wait_staged();
+      __syncthreads();
+    }
     if (nb >= 0) {
       const T* un_src = U + s * SE + (size_t)nb * NM;
 #pragma unroll
@@ -322,7 +405,7 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
           const int m = face_mode<D, Q>(a, i, J);
-          const T v = un_src[m];
+          const T v = STAGED ? staged<D, P, T, EB>(sm, tid, m) : un_src[m];
           a0 += T(tb.E[1 - sg][i]) * v;
           a1 += T(tb.dE[1 - sg][i]) * v;
           // u_o - u_n formed mode by mode: the i = 0 terms (value 1 at both ends)
@@ -334,7 +417,9 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
         jm[J] = a2;
       }
     }
-    // publish point values needed by the face point pass
+    // publish point values needed by the face point pass (the exchange slots
+    // overlay the staging area: everyone has finished reading it)
+    if constexpr (STAGED) __syncthreads();
     const int b0 = a == 0 ? 1 : 0, b1 = a == 2 ? 1 : 2;   // tangential axes
     const double(*Tb0)[CDG2_MAXQ] = tb.B;
     if (vslot >= 0) {
@@ -458,7 +543,27 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
   }
 
   // ---- M^{-1}, stage combination, store ---------------------------------------------
-  if (live) {
+  if constexpr (STAGED) {
+    // values into the staging area, then coalesced stores (and u0 loads) by
+    // consecutive lanes over consecutive modes of consecutive cells
+    const T ivol = T(1.0 / g.vol);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NM; ++m) sm.buf[tid * NM + m] = stage == 0 ? R[m] * ivol : cb * (u[m] + dt * (R[m] * ivol));
+    __syncthreads();
+    constexpr int TOT = 6 * EB * NM, PERS = EB * NM;
+    for (int i = tid; i < TOT; i += NT) {
+      const int sp = i / PERS, rem = i - sp * PERS;
+      const int l = rem / NM, m = rem - l * NM;
+      const int cl = sm.cell[l];
+      if (cl < 0) continue;
+      const size_t gi = sp * SE + (size_t)cl * NM + m;
+      T v = sm.buf[i];
+      if (stage != 0 && ca != T(0)) v += ca * U0[gi];
+      if (!isfinite(v)) flag |= FLAG_NONFINITE;
+      out[gi] = v;
+    }
+  } else if (live) {
     const T ivol = T(1.0 / g.vol);
     T* dst = out + s * SE + (size_t)e * NM;
     if (stage == 0) {
