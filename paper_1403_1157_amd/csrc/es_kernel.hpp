@@ -18,7 +18,10 @@
 //
 // Mapping:
 //   * a workgroup owns EB consecutive cells; thread (s, el) keeps the modes and
-//     the modal residual of species s of cell el in registers;
+//     the modal residual of species s of cell el in registers (in 3D the
+//     workgroup first moves all its cells' modes into LDS with coalesced
+//     load-to-LDS instructions, and its results leave through LDS with coalesced
+//     stores);
 //   * everything linear in U is applied by that thread alone, exactly, in modal
 //     form: -a_s int grad u . grad phi (1D stiffness per axis), the face
 //     consistency / symmetry / lifting terms (tangential-modal traces of the
@@ -46,7 +49,8 @@ struct EsSz {
 };
 
 // LDS: one union buffer, reused by the volume layers and by the faces, and in 3D
-// also as the staging area of coalesced loads and stores of whole cells' modes.
+// also as the staging area of the coalesced load of the workgroup's own cells'
+// modes (all six species) and of the coalesced store of the results.
 // Staged loads move chunks of CB bytes (16, or 12 when a cell's modes are not a
 // multiple of 16 bytes), NCH per (cell, species); the load-to-LDS instruction
 // places lane t's chunk at 16 t bytes for both sizes, so chunk k of thread
@@ -84,27 +88,26 @@ __device__ __forceinline__ T staged(const EsSmem<D, P, T, EB>& sm, int g, int m)
   }
 }
 
-// Start loading the modes of the cells idx[l * istride] (l < EB; outside [0, E):
+// Start loading the modes of the workgroup's cells sm.cell[l] (outside [0, E):
 // none, cell 0 is loaded and not used) of all six species straight into the
 // staging area, without registers in flight: consecutive lanes take consecutive
-// chunks, so each load instruction reads whole cache lines of consecutive cells.
+// chunks, so each load instruction reads whole cache lines of consecutive cells
+// (one lane per cell and 216-byte modes would put every lane on its own line).
 // The caller waits (vmcnt) and synchronises before reading.
 template <int D, int P, typename T, int EB>
-__device__ __forceinline__ void stage_modes(const T* U, size_t SE, int E, EsSmem<D, P, T, EB>& sm,
-                                            const int* idx, int istride, int tid) {
+__device__ __forceinline__ void stage_modes(const T* U, size_t SE, int E, EsSmem<D, P, T, EB>& sm, int tid) {
   using SM = EsSmem<D, P, T, EB>;
   constexpr int NM = EsSz<D, P>::NM, NT = 6 * EB, CB = SM::CB, NCH = SM::NCH;
   static_assert(SM::BYTES % CB == 0, "chunking");
   constexpr int PER = EB * NCH;                 // chunks per species
   constexpr int RR = (PER + NT - 1) / NT;
   unsigned char* base = reinterpret_cast<unsigned char*>(sm.buf);
-  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // earlier LDS reads of the area are done
 #pragma unroll
   for (int r = 0; r < RR; ++r) {
     const int ch = r * NT + tid;
     if (ch < PER) {
       const int l = ch / NCH, k = ch % NCH;
-      const int n = idx[l * istride];
+      const int n = sm.cell[l];
       const char* src = reinterpret_cast<const char*>(U + (size_t)(n >= 0 && n < E ? n : 0) * NM) + k * CB;
 #pragma unroll
       for (int sp = 0; sp < 6; ++sp) {
@@ -216,7 +219,7 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
   if constexpr (STAGED) {
     if (tid < EB) sm.cell[tid] = e0 + tid < E ? cell_of<D>(g, e0 + tid) : -1;
     __syncthreads();
-    stage_modes<D, P, T, EB>(U, SE, E, sm, sm.cell, 1, tid);
+    stage_modes<D, P, T, EB>(U, SE, E, sm, tid);
     wait_staged();
     __syncthreads();
 #pragma unroll
@@ -374,7 +377,7 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
     __syncthreads();
     // 3D: the neighbours' modes arrive in the staging area while the own traces
     // are formed
-    if constexpr (STAGED) stage_modes<D, P, T, EB>(U, SE, E, sm, &sm.nb[0][f], NFACE, tid);
+
     const int nb = sm.nb[el][f];
     // tangential-modal traces: value / d_a of own and neighbour, accurate jump
     T uo[NF], duo[NF], un[NF], dun[NF], jm[NF];
@@ -393,10 +396,6 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
       dun[J] = T(0);
       jm[J] = T(0);
     }
-    if constexpr (STAGED) {
-      wait_staged();
-      __syncthreads();
-    }
     if (nb >= 0) {
       const T* un_src = U + s * SE + (size_t)nb * NM;
 #pragma unroll
@@ -405,7 +404,7 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
           const int m = face_mode<D, Q>(a, i, J);
-          const T v = STAGED ? staged<D, P, T, EB>(sm, tid, m) : un_src[m];
+          const T v = un_src[m];
           a0 += T(tb.E[1 - sg][i]) * v;
           a1 += T(tb.dE[1 - sg][i]) * v;
           // u_o - u_n formed mode by mode: the i = 0 terms (value 1 at both ends)
@@ -419,7 +418,6 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
     }
     // publish point values needed by the face point pass (the exchange slots
     // overlay the staging area: everyone has finished reading it)
-    if constexpr (STAGED) __syncthreads();
     const int b0 = a == 0 ? 1 : 0, b1 = a == 2 ? 1 : 2;   // tangential axes
     const double(*Tb0)[CDG2_MAXQ] = tb.B;
     if (vslot >= 0) {
