@@ -156,6 +156,22 @@ int cdg2_apply_adjoint(cdg2_handle* h, const void* U, const void* w, void* JTw, 
 int cdg2_rk_step_adjoint(cdg2_handle* h, const void* U_n, const void* lam_np1, void* lam_n, double dt,
                          double* dtheta_acc);
 
+/* Discrete adjoint of nsteps SSP-RK3 steps of size dt started from U_start (one
+ * checkpoint segment of a reverse sweep, Section 3.2 time stepping): recomputes
+ * the segment forward once, keeping U^n, U1 and U2 of every step in a library
+ * workspace (3 nsteps states, grown on demand with hipMalloc and kept until
+ * cdg2_destroy), then applies the step adjoint of cdg2_rk_step_adjoint from the
+ * last step to the first.  lam (device, cdg2_num_dofs entries) holds
+ * dL/dU^{start+nsteps} on entry and dL/dU^{start} on return; it must not
+ * overlap U_start.  dtheta_acc: NULL or a DEVICE array of CDG2_NDIFF doubles to
+ * which the parameter derivatives of the whole segment are ADDED in stream order
+ * (the per-workgroup partial sums of all 3 nsteps adjoint launches are summed
+ * in a fixed order, then reduced once).  Same results as nsteps calls of
+ * cdg2_rk_step_adjoint up to the order of the parameter sums; all work is
+ * enqueued on the handle's stream without host waits.  nsteps >= 1. */
+int cdg2_rk_adjoint_segment(cdg2_handle* h, const void* U_start, int nsteps, double dt, void* lam,
+                            double* dtheta_acc);
+
 /* ---- batched instances ---------------------------------------------------------
  * Many independent 2D instances (own grid, order 1..3, coefficients; FP64) are
  * advanced together: one persistent launch per SSP-RK3 stage walks a work list

@@ -2,9 +2,10 @@
 
 :class:`CDG2RK` runs ``nsteps`` SSP-RK3 steps of the HIP operator in its forward
 pass, keeping a checkpoint of the state every ``ckpt`` steps.  Its backward pass
-walks the checkpoints in reverse: it recomputes the states of one segment with
-the forward kernels and then applies the discrete adjoint of each step
-(``cdg2_rk_step_adjoint``), accumulating the parameter derivatives.  It returns
+walks the checkpoints in reverse; for each segment one library call
+(``cdg2_rk_adjoint_segment``) recomputes the segment's states and stages with the
+forward kernels and applies the discrete adjoint of each step from the last to
+the first, accumulating the parameter derivatives on the device.  It returns
 gradients with respect to the initial state and to the 21 differentiable
 coefficients (diffusion, chemotaxis, reactions).  The arithmetic runs in the
 library; this module only orders the calls and holds the checkpoints.
@@ -60,13 +61,8 @@ class CDG2RK(torch.autograd.Function):
         for seg in reversed(range(nseg)):
             start = seg * ckpt
             end = min(start + ckpt, nsteps)
-            states = [ctx.checkpoints[seg]]
-            U = states[0].clone()
-            for _ in range(start, end - 1):
-                op.rk_step(U, dt, 1)
-                states.append(U.clone())
-            for n in reversed(range(start, end)):
-                op.rk_step_adjoint(states[n - start], lam, lam, dt, dth)
+            # recompute of the segment and its reverse sweep, enqueued by the library
+            op.rk_adjoint_segment(ctx.checkpoints[seg], end - start, dt, lam, dth)
         op.sync()
         return lam, dth.cpu(), None, None, None, None, None
 

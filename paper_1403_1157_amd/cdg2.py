@@ -74,6 +74,7 @@ def lib():
     L.cdg2_rho_hat.restype = _d
     L.cdg2_apply_adjoint.argtypes = [P, P, P, P, ctypes.POINTER(_d)]
     L.cdg2_rk_step_adjoint.argtypes = [P, P, P, P, _d, ctypes.POINTER(_d)]
+    L.cdg2_rk_adjoint_segment.argtypes = [P, P, ctypes.c_int, _d, P, ctypes.POINTER(_d)]
     L.cdg2_batch_create.argtypes = [ctypes.POINTER(cdg2_config), ctypes.c_int, ctypes.POINTER(P)]
     L.cdg2_batch_destroy.argtypes = [P]
     L.cdg2_batch_set_stream.argtypes = [P, P]
@@ -88,7 +89,8 @@ def lib():
     L.cdg2_last_error.restype = ctypes.c_char_p
     for name in ("cdg2_create", "cdg2_destroy", "cdg2_set_stream", "cdg2_set_coeffs",
                  "cdg2_apply_operator", "cdg2_rk_step", "cdg2_max_dt", "cdg2_sync",
-                 "cdg2_apply_adjoint", "cdg2_rk_step_adjoint", "cdg2_batch_create",
+                 "cdg2_apply_adjoint", "cdg2_rk_step_adjoint", "cdg2_rk_adjoint_segment",
+                 "cdg2_batch_create",
                  "cdg2_batch_destroy", "cdg2_batch_set_stream", "cdg2_batch_set_schedule",
                  "cdg2_batch_rk", "cdg2_batch_sync"):
         getattr(L, name).restype = ctypes.c_int
@@ -183,6 +185,16 @@ def cdg2_rk_step_adjoint(h, Un_ptr: int, lam_np1_ptr: int, lam_n_ptr: int, dt: f
                                       ctypes.c_void_p(lam_n_ptr), float(dt),
                                       ctypes.cast(ctypes.c_void_p(dtheta_acc_ptr or None),
                                                   ctypes.POINTER(_d))))
+
+
+def cdg2_rk_adjoint_segment(h, U_start_ptr: int, nsteps: int, dt: float, lam_ptr: int,
+                            dtheta_acc_ptr: int = 0):
+    """lam_ptr: device buffer, dL/dU at the end of the segment in, at its start out;
+    dtheta_acc_ptr: 0 or the device address of 21 float64 accumulators."""
+    _check(lib().cdg2_rk_adjoint_segment(h, ctypes.c_void_p(U_start_ptr), int(nsteps), float(dt),
+                                         ctypes.c_void_p(lam_ptr),
+                                         ctypes.cast(ctypes.c_void_p(dtheta_acc_ptr or None),
+                                                     ctypes.POINTER(_d))))
 
 
 def cdg2_batch_create(cfgs) -> ctypes.c_void_p:
@@ -292,6 +304,19 @@ class Operator:
             ptr = dtheta_acc.data_ptr()
         cdg2_rk_step_adjoint(self.h, self._arg(U_n), self._arg(lam_np1), self._arg(lam_n), dt, ptr)
         return lam_n
+
+    def rk_adjoint_segment(self, U_start, nsteps, dt, lam, dtheta_acc=None):
+        """Adjoint of nsteps steps from U_start: lam (in place) goes from dL/dU at the
+        end of the segment to dL/dU at its start; dtheta_acc as in rk_step_adjoint."""
+        self._stream()
+        ptr = 0
+        if dtheta_acc is not None:
+            if not (dtheta_acc.is_cuda and dtheta_acc.dtype == torch.float64
+                    and dtheta_acc.is_contiguous() and dtheta_acc.numel() == 21):
+                raise ValueError("dtheta_acc must be a contiguous CUDA float64 tensor of 21 entries")
+            ptr = dtheta_acc.data_ptr()
+        cdg2_rk_adjoint_segment(self.h, self._arg(U_start), nsteps, dt, self._arg(lam), ptr)
+        return lam
 
     def set_coeffs(self, coeffs: dict) -> None:
         cdg2_set_coeffs(self.h, coeffs)

@@ -46,7 +46,7 @@ struct AdjSmem {
   static constexpr int N = VOL > FAC ? VOL : FAC;
   T buf[N];
   int nb[EB][2 * D];
-  double red[6 * EB];
+  double red[(6 * EB + 63) / 64 * CDG2_NDIFF];
 };
 
 // Parameter-derivative slots (indices into the 21 differentiable coefficients).
@@ -589,18 +589,30 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
   if (flag) atomicOr(flags, flag);
 
   // ---- deterministic per-workgroup reduction of the parameter derivatives -----------
-  // (unrolled so that th[] is indexed statically and stays in registers)
+  // A butterfly over the 64 lanes of each wavefront (fixed pairing), then the
+  // wavefront sums in order; unrolled so that th[] stays in registers.
   if (want_theta) {
+    static_assert(NT % 64 == 0, "whole wavefronts");
+    constexpr int NW = NT / 64;
+    const int lane = tid & 63, wv = tid >> 6;
 #pragma unroll
     for (int j = 0; j < CDG2_NDIFF; ++j) {
-      __syncthreads();
-      sm.red[tid] = th[j] + (j < 6 && j == s ? thd : 0.0);
-      __syncthreads();
-      if (tid == 0) {
-        double acc = 0.0;
-        for (int k = 0; k < NT; ++k) acc += sm.red[k];
-        part[(size_t)blk * CDG2_NDIFF + j] = acc * (double)cj;
-      }
+      double v = th[j] + (j < 6 && j == s ? thd : 0.0);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      th[j] = v;
+    }
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < CDG2_NDIFF; ++j) sm.red[wv * CDG2_NDIFF + j] = th[j];
+    }
+    __syncthreads();
+    if (tid < CDG2_NDIFF) {
+      double acc = 0.0;
+      for (int k = 0; k < NW; ++k) acc += sm.red[k * CDG2_NDIFF + tid];
+      double* dst = part + (size_t)blk * CDG2_NDIFF + tid;
+      *dst = want_theta == 2 ? *dst + acc * (double)cj : acc * (double)cj;
     }
   }
 }

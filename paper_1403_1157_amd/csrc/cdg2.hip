@@ -56,6 +56,8 @@ struct cdg2_handle {
   double* part = nullptr;              // per-workgroup parameter partials
   double* dth = nullptr;               // device accumulator of parameter derivatives
   int nblk_adj = 0;
+  void* seg = nullptr;                 // adjoint segment workspace (3 states per step)
+  size_t seg_cap = 0;                  // its capacity in states
   hipStream_t stream = nullptr;
   double rho_hat = 0.0;
 };
@@ -179,14 +181,14 @@ struct AdjCfg {
 
 template <int D, int P, typename T>
 hipError_t launch_adj(cdg2_handle* h, const void* U, const void* W, void* out, double cw, double cj,
-                      const void* X2, double c2, const void* X3, double c3, int want_theta) {
+                      const void* X2, double c2, const void* X3, double c3, int want_theta, bool reduce) {
   constexpr int EB = AdjCfg<D, P>::EB;
   int nb = (h->geo.E + EB - 1) / EB;
   hipLaunchKernelGGL((adj_kernel<D, P, T, EB>), dim3(nb), dim3(6 * EB), 0, h->stream, h->dprm, (const T*)U,
                      (const T*)W, (T*)out, (T)cw, (T)cj, (const T*)X2, (T)c2, (const T*)X3, (T)c3, h->part,
                      want_theta, h->flags);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !want_theta) return e;
+  if (e != hipSuccess || !reduce) return e;
   hipLaunchKernelGGL(theta_reduce_kernel, dim3(CDG2_NDIFF), dim3(256), 0, h->stream, (const double*)h->part, nb,
                      h->dth);
   return hipGetLastError();
@@ -194,23 +196,26 @@ hipError_t launch_adj(cdg2_handle* h, const void* U, const void* W, void* out, d
 
 template <typename T>
 hipError_t dispatch_adj(cdg2_handle* h, const void* U, const void* W, void* out, double cw, double cj,
-                        const void* X2, double c2, const void* X3, double c3, int want_theta) {
+                        const void* X2, double c2, const void* X3, double c3, int want_theta, bool reduce) {
   switch (h->dim * 10 + h->p) {
-    case 21: return launch_adj<2, 1, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta);
-    case 22: return launch_adj<2, 2, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta);
-    case 23: return launch_adj<2, 3, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta);
-    case 24: return launch_adj<2, 4, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta);
-    case 31: return launch_adj<3, 1, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta);
-    case 32: return launch_adj<3, 2, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta);
-    case 33: return launch_adj<3, 3, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta);
+    case 21: return launch_adj<2, 1, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta, reduce);
+    case 22: return launch_adj<2, 2, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta, reduce);
+    case 23: return launch_adj<2, 3, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta, reduce);
+    case 24: return launch_adj<2, 4, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta, reduce);
+    case 31: return launch_adj<3, 1, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta, reduce);
+    case 32: return launch_adj<3, 2, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta, reduce);
+    case 33: return launch_adj<3, 3, T>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta, reduce);
   }
   return hipErrorInvalidValue;
 }
 
+// want_theta: 0 no parameter derivatives, 1 per-workgroup partials written,
+// 2 added to the partials of the previous call; reduce: sum the partials into
+// h->dth after the launch.
 hipError_t run_adj(cdg2_handle* h, const void* U, const void* W, void* out, double cw, double cj,
-                   const void* X2, double c2, const void* X3, double c3, int want_theta) {
-  return h->fp32 ? dispatch_adj<float>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta)
-                 : dispatch_adj<double>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta);
+                   const void* X2, double c2, const void* X3, double c3, int want_theta, bool reduce) {
+  return h->fp32 ? dispatch_adj<float>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta, reduce)
+                 : dispatch_adj<double>(h, U, W, out, cw, cj, X2, c2, X3, c3, want_theta, reduce);
 }
 
 // Adjoint buffers, allocated on the first adjoint call.
@@ -302,6 +307,7 @@ int cdg2_destroy(cdg2_handle* h) {
     if (h->adj[k]) (void)hipFree(h->adj[k]);
   if (h->part) (void)hipFree(h->part);
   if (h->dth) (void)hipFree(h->dth);
+  if (h->seg) (void)hipFree(h->seg);
   delete h;
   return CDG2_OK;
 }
@@ -358,7 +364,7 @@ int cdg2_apply_adjoint(cdg2_handle* h, const void* U, const void* w, void* JTw, 
   int rc = ensure_adjoint(h);
   if (rc) return rc;
   if (dtheta) HIP_TRY(hipMemsetAsync(h->dth, 0, CDG2_NDIFF * sizeof(double), h->stream));
-  HIP_TRY(run_adj(h, U, w, JTw, 0.0, 1.0, nullptr, 0.0, nullptr, 0.0, dtheta != nullptr));
+  HIP_TRY(run_adj(h, U, w, JTw, 0.0, 1.0, nullptr, 0.0, nullptr, 0.0, dtheta != nullptr, dtheta != nullptr));
   if (dtheta) {
     HIP_TRY(hipMemcpyAsync(dtheta, h->dth, CDG2_NDIFF * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -385,12 +391,67 @@ int cdg2_rk_step_adjoint(cdg2_handle* h, const void* U_n, const void* lam_np1, v
   //   lam1 = 1/4 lam2 + 1/4 dt J(U1)^T lam2
   //   lam_n = 1/3 lam3 + 3/4 lam2 + lam1 + dt J(U_n)^T lam1
   if (e == hipSuccess)
-    e = run_adj(h, h->stage[1], lam_np1, h->adj[0], 2.0 / 3.0, 2.0 / 3.0 * dt, nullptr, 0.0, nullptr, 0.0, th);
+    e = run_adj(h, h->stage[1], lam_np1, h->adj[0], 2.0 / 3.0, 2.0 / 3.0 * dt, nullptr, 0.0, nullptr, 0.0, th,
+                false);
   if (e == hipSuccess)
-    e = run_adj(h, h->stage[0], h->adj[0], h->adj[1], 0.25, 0.25 * dt, nullptr, 0.0, nullptr, 0.0, th);
-  if (e == hipSuccess) e = run_adj(h, U_n, h->adj[1], lam_n, 1.0, dt, lam_np1, 1.0 / 3.0, h->adj[0], 0.75, th);
+    e = run_adj(h, h->stage[0], h->adj[0], h->adj[1], 0.25, 0.25 * dt, nullptr, 0.0, nullptr, 0.0, th ? 2 : 0,
+                false);
+  // the three stages' partials are summed per workgroup, then reduced once
+  if (e == hipSuccess)
+    e = run_adj(h, U_n, h->adj[1], lam_n, 1.0, dt, lam_np1, 1.0 / 3.0, h->adj[0], 0.75, th ? 2 : 0, th);
   h->dth = acc_save;
   if (e != hipSuccess) return fail(CDG2_EHIP, "adjoint step launch: %s", hipGetErrorString(e));
+  return CDG2_OK;
+}
+
+int cdg2_rk_adjoint_segment(cdg2_handle* h, const void* U_start, int nsteps, double dt, void* lam,
+                            double* dtheta_acc) {
+  if (!h || !U_start || !lam) return fail(CDG2_EINVAL, "NULL argument");
+  if (nsteps < 1) return fail(CDG2_EINVAL, "nsteps must be >= 1 (got %d)", nsteps);
+  if (!std::isfinite(dt)) return fail(CDG2_EINVAL, "dt is not finite");
+  const size_t esz = h->fp32 ? 4 : 8;
+  const size_t bytes = h->ndof * esz;
+  if (overlap(lam, U_start, bytes)) return fail(CDG2_EINVAL, "lam overlaps U_start");
+  int rc = ensure_adjoint(h);
+  if (rc) return rc;
+  const size_t need = 3 * (size_t)nsteps;
+  if (need > h->seg_cap) {
+    // the stream may still use the old workspace
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (h->seg) (void)hipFree(h->seg);
+    h->seg = nullptr;
+    h->seg_cap = 0;
+    if (hipMalloc(&h->seg, need * bytes) != hipSuccess)
+      return fail(CDG2_ENOMEM, "hipMalloc of the adjoint segment workspace (%zu states) failed", need);
+    h->seg_cap = need;
+  }
+  auto st = [&](size_t k) { return (void*)((char*)h->seg + k * bytes); };
+  // forward: X^n at 3n, U1 at 3n+1, U2 at 3n+2; stage 3 writes X^{n+1} at 3n+3
+  // (not needed after the last step)
+  hipError_t e = hipMemcpyAsync(st(0), U_start, bytes, hipMemcpyDeviceToDevice, h->stream);
+  for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
+    e = run_op(h, st(3 * n), nullptr, st(3 * n + 1), dt, 0.0, 1.0, 1);
+    if (e == hipSuccess) e = run_op(h, st(3 * n + 1), st(3 * n), st(3 * n + 2), dt, 0.75, 0.25, 2);
+    if (e == hipSuccess && n + 1 < nsteps)
+      e = run_op(h, st(3 * n + 2), st(3 * n), st(3 * n + 3), dt, 1.0 / 3.0, 2.0 / 3.0, 3);
+  }
+  // reverse sweep (recurrences of cdg2_rk_step_adjoint), lam in place
+  const int th = dtheta_acc != nullptr;
+  double* acc_save = h->dth;
+  if (th) h->dth = dtheta_acc;
+  for (int n = nsteps - 1; n >= 0 && e == hipSuccess; --n) {
+    const int first = th && n == nsteps - 1 ? 1 : th ? 2 : 0;
+    e = run_adj(h, st(3 * n + 2), lam, h->adj[0], 2.0 / 3.0, 2.0 / 3.0 * dt, nullptr, 0.0, nullptr, 0.0, first,
+                false);
+    if (e == hipSuccess)
+      e = run_adj(h, st(3 * n + 1), h->adj[0], h->adj[1], 0.25, 0.25 * dt, nullptr, 0.0, nullptr, 0.0,
+                  th ? 2 : 0, false);
+    if (e == hipSuccess)
+      e = run_adj(h, st(3 * n), h->adj[1], lam, 1.0, dt, lam, 1.0 / 3.0, h->adj[0], 0.75, th ? 2 : 0,
+                  th && n == 0);
+  }
+  h->dth = acc_save;
+  if (e != hipSuccess) return fail(CDG2_EHIP, "adjoint segment launch: %s", hipGetErrorString(e));
   return CDG2_OK;
 }
 

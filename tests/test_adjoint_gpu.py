@@ -80,6 +80,40 @@ def test_rk_step_adjoint_parity(dim, n, p):
     theta_close(dth.cpu().numpy(), th.grad[:21].numpy(), 1e-11)
 
 
+@pytest.mark.parametrize("dim,n,p,nsteps", [(2, (8, 6), 2, 7), (2, (5, 6), 3, 1), (3, (4, 3, 4), 2, 3)])
+def test_adjoint_segment_matches_step_adjoints(dim, n, p, nsteps):
+    """cdg2_rk_adjoint_segment against nsteps calls of cdg2_rk_step_adjoint on the
+    states of the same forward run: the same kernels on the same inputs, so lam
+    agrees to rounding-free equality up to the parameter sums' order (dtheta)."""
+    c = strong()
+    U, cfg = make_case(dim, n, p, key=(6,), coeffs=c)
+    op = gpu_op(cfg)
+    Ud = U.to(DEV)
+    dt = op.max_dt(Ud, 0.9)
+    states = [Ud.clone()]
+    X = Ud.clone()
+    for _ in range(nsteps - 1):
+        op.rk_step(X, dt, 1)
+        states.append(X.clone())
+    g = torch.Generator().manual_seed(11)
+    lam0 = torch.randn(U.shape, generator=g, dtype=torch.float64).to(DEV)
+    lam_ref = lam0.clone()
+    dth_ref = torch.zeros(21, dtype=torch.float64, device=DEV)
+    for k in reversed(range(nsteps)):
+        op.rk_step_adjoint(states[k], lam_ref, lam_ref, dt, dth_ref)
+    lam = lam0.clone()
+    dth = torch.zeros(21, dtype=torch.float64, device=DEV)
+    op.rk_adjoint_segment(Ud, nsteps, dt, lam, dth)
+    op.sync()
+    assert torch.equal(lam, lam_ref)
+    theta_close(dth.cpu().numpy(), dth_ref.cpu().numpy(), 1e-13)
+    # a second, longer segment on the same handle grows the workspace
+    lam2 = lam0.clone()
+    op.rk_adjoint_segment(Ud, nsteps + 2, dt, lam2)
+    op.sync()
+    assert torch.isfinite(lam2).all()
+
+
 def test_checkpointed_gradient_matches_oracle():
     """Gradient of the mismatch loss through 12 steps (checkpoints every 5) against
     the oracle's autograd gradient through the same steps."""
