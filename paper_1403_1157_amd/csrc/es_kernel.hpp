@@ -48,23 +48,27 @@ struct EsSz {
   static constexpr int NFQ = 14;           // face exchange: 4 values x 2 sides, 3 d_n x 2 sides
 };
 
-// LDS: one union buffer, reused by the volume layers and by the faces, and in 3D
+// LDS: one union buffer, reused by the volume layers and by the faces, and (3D)
 // also as the staging area of the coalesced load of the workgroup's own cells'
 // modes (all six species) and of the coalesced store of the results.
-// Staged loads move chunks of CB bytes (16, or 12 when a cell's modes are not a
-// multiple of 16 bytes), NCH per (cell, species); the load-to-LDS instruction
-// places lane t's chunk at 16 t bytes for both sizes, so chunk k of thread
-// g = (s, l) sits at byte 16 (g NCH + k) (a 12-byte chunk leaves 4 bytes unused).
+// Staged loads move chunks of CB bytes (16; 12 when a cell's modes are not a
+// multiple of 16 bytes; else 4), NCH per (cell, species).  The load-to-LDS
+// instruction places lane t's chunk at LS t bytes, LS = 16 for 12- and 16-byte
+// chunks and 4 for 4-byte ones, so chunk k of thread g = (s, l) sits at byte
+// LS (g NCH + k) (a 12-byte chunk leaves 4 bytes unused).
 template <int D, int P, typename T, int EB>
 struct EsSmem {
   using S = EsSz<D, P>;
+  // 3D only: in 2D (72 to 200 bytes per (cell, species)) the staging measured no
+  // gain and its LDS lowered the occupancy of the batched kernel
   static constexpr bool STAGED = D == 3;
   static constexpr int BYTES = S::NM * (int)sizeof(T);
-  static constexpr int CB = BYTES % 16 == 0 ? 16 : 12;
+  static constexpr int CB = BYTES % 16 == 0 ? 16 : BYTES % 12 == 0 ? 12 : 4;
+  static constexpr int LS = CB == 4 ? 4 : 16;
   static constexpr int NCH = BYTES / CB;
   static constexpr int VOL = EB * S::NVQ * S::PC;
   static constexpr int FAC = EB * S::NFQ * S::NF;
-  static constexpr int STG = STAGED ? 6 * EB * NCH * 16 / (int)sizeof(T) : 0;
+  static constexpr int STG = STAGED ? 6 * EB * NCH * LS / (int)sizeof(T) : 0;
   static constexpr int N0 = VOL > FAC ? VOL : FAC;
   static constexpr int N = N0 > STG ? N0 : STG;
   int nb[EB][2 * D];
@@ -76,15 +80,19 @@ struct EsSmem {
 template <int D, int P, typename T, int EB>
 __device__ __forceinline__ T staged(const EsSmem<D, P, T, EB>& sm, int g, int m) {
   using SM = EsSmem<D, P, T, EB>;
-  constexpr int CB = SM::CB, NCH = SM::NCH;
-  const int b = m * (int)sizeof(T), j = b / CB, r = b % CB;
+  constexpr int CB = SM::CB, NCH = SM::NCH, LS = SM::LS;
   const unsigned char* base = reinterpret_cast<const unsigned char*>(sm.buf);
-  if (r + (int)sizeof(T) <= CB) {
-    return *reinterpret_cast<const T*>(base + (g * NCH + j) * 16 + r);
-  } else {   // a double split over two chunks, 4 + 4 bytes
-    const int lo = *reinterpret_cast<const int*>(base + (g * NCH + j) * 16 + r);
-    const int hi = *reinterpret_cast<const int*>(base + (g * NCH + j + 1) * 16);
-    return T(__hiloint2double(hi, lo));
+  if constexpr (LS == CB) {   // contiguous segments
+    return *reinterpret_cast<const T*>(base + g * SM::BYTES + m * (int)sizeof(T));
+  } else {
+    const int b = m * (int)sizeof(T), j = b / CB, r = b % CB;
+    if (r + (int)sizeof(T) <= CB) {
+      return *reinterpret_cast<const T*>(base + (g * NCH + j) * LS + r);
+    } else {   // a double split over two chunks, 4 + 4 bytes
+      const int lo = *reinterpret_cast<const int*>(base + (g * NCH + j) * LS + r);
+      const int hi = *reinterpret_cast<const int*>(base + (g * NCH + j + 1) * LS);
+      return T(__hiloint2double(hi, lo));
+    }
   }
 }
 
@@ -102,6 +110,9 @@ __device__ __forceinline__ void stage_modes(const T* U, size_t SE, int E, EsSmem
   constexpr int PER = EB * NCH;                 // chunks per species
   constexpr int RR = (PER + NT - 1) / NT;
   unsigned char* base = reinterpret_cast<unsigned char*>(sm.buf);
+  // the instruction's LDS address is per wavefront (lane t of the wavefront at
+  // LS t): offset each wavefront by its first thread
+  const int wbase = __builtin_amdgcn_readfirstlane((tid / 64) * 64);
 #pragma unroll
   for (int r = 0; r < RR; ++r) {
     const int ch = r * NT + tid;
@@ -111,12 +122,14 @@ __device__ __forceinline__ void stage_modes(const T* U, size_t SE, int E, EsSmem
       const char* src = reinterpret_cast<const char*>(U + (size_t)(n >= 0 && n < E ? n : 0) * NM) + k * CB;
 #pragma unroll
       for (int sp = 0; sp < 6; ++sp) {
-        auto* dst = (__attribute__((address_space(3))) void*)(base + (sp * PER + r * NT) * 16);
+        auto* dst = (__attribute__((address_space(3))) void*)(base + (sp * PER + r * NT + wbase) * SM::LS);
         const char* sps = src + (size_t)sp * SE * sizeof(T);
         if constexpr (CB == 16) {
           __builtin_amdgcn_global_load_lds(sps, dst, 16, 0, 0);
-        } else {
+        } else if constexpr (CB == 12) {
           __builtin_amdgcn_global_load_lds(sps, dst, 12, 0, 0);
+        } else {
+          __builtin_amdgcn_global_load_lds(sps, dst, 4, 0, 0);
         }
       }
     }
