@@ -44,6 +44,7 @@ APPLY_CASES = [
     (3, (6, 5, 4), 2, "strong", None, "all", (0.25, 0.5)),
     (3, (4, 3, 5), 3, "strong", None, "cells", (0, 1)),
     (3, (3, 4, 2), 2, "strong", 1, "all", (0, 1)),
+    (3, (4, 3, 11), 2, "strong", None, "all", (0, 1)),      # two z-slabs of the processing order, ragged
 ]
 
 
