@@ -15,6 +15,8 @@ atherosclerotic plaque formation using higher order DG schemes"):
   r_e formed on K^-_e and lift factor chi_e = N/2);
 * f(U) = M^{-1} L_h(U) of Section 3.2;
 * explicit SSP-RK3 (Shu-Osher form) used as the time integrator;
+* the implicit DIRK integrator of Section 3.2 (SDIRK of order 2, 3, 4), each
+  stage solved by Newton's method with the exact (autograd) Jacobian;
 * a CFL time step.
 
 Everything is evaluated by DIRECT quadrature sums (u(x_q) = sum_m U_m phi_m(x_q),
@@ -463,6 +465,60 @@ class Oracle:
             t += dt
         return U
 
+    # -- implicit DIRK (Section 3.2: DIRK of order 2-4 solved by Newton) --------
+    def dirk_step(self, U, dt, order, tol=1e-13, maxit=60, theta=None):
+        """One step of the L-stable, stiffly accurate SDIRK scheme of the given
+        order (sdirk_tableau): for each stage i the stage value X_i solves
+            X_i - dt a_ii f(X_i) = U^n + dt sum_{j<i} a_ij f(X_j),
+        then U^{n+1} = U^n + dt sum_i b_i K_i with K_i = (X_i - rhs_i) / (dt a_ii)
+        (= f(X_i) once the stage equation holds).  Each stage equation
+        G(X) = X - dt a_ii f(X) - rhs = 0 is solved to
+        ||G|| <= tol (||X|| + dt a_ii ||f(X)||) (2-norms over all modes: relative
+        to the size of its terms) by Newton's method with the exact Jacobian of
+        f (autograd), kept fixed within a stage and recomputed if the iteration
+        stalls.  Returns (U^{n+1}, total Newton iterations)."""
+        A, b, _ = sdirk_tableau(order)
+        shape = U.shape
+        n = U.numel()
+        eye = torch.eye(n, dtype=DT)
+
+        def jac(X):
+            J = torch.autograd.functional.jacobian(
+                lambda y: self.apply(y.reshape(shape), theta).reshape(-1), X.reshape(-1), vectorize=True)
+            return J.reshape(n, n)
+
+        K = []
+        iters = 0
+        for i in range(len(b)):
+            rhs = U.clone()
+            for j in range(i):
+                rhs = rhs + dt * A[i][j] * K[j]
+            g = A[i][i]
+            X = rhs.clone()
+            lu = None
+            prev = None
+            for _ in range(maxit):
+                F = self.apply(X, theta)
+                G = X - dt * g * F - rhs
+                r = float(G.norm())
+                if r <= tol * (float(X.norm()) + dt * g * float(F.norm())):
+                    break
+                if lu is None or (prev is not None and r > 0.5 * prev):
+                    lu = torch.linalg.lu_factor(eye - dt * g * jac(X))
+                prev = r
+                d = torch.linalg.lu_solve(*lu, -G.reshape(-1, 1)).reshape(shape)
+                X = X + d
+                iters += 1
+            else:
+                raise RuntimeError("oracle DIRK stage did not converge")
+            # stage derivative from the solved stage equation: equal to f(X_i) at
+            # convergence, and free of dt-amplified rounding when dt is large
+            K.append((X - rhs) / (dt * g))
+        out = U.clone()
+        for i in range(len(b)):
+            out = out + dt * b[i] * K[i]
+        return out, iters
+
     # -- CFL time step ----------------------------------------------------------
     def spectral_constant(self, ncell: int = 4) -> float:
         """rho_hat: spectral radius of M^{-1} K for the pure diffusion operator
@@ -541,6 +597,39 @@ class Oracle:
         ex = func(x)
         err = torch.einsum("q,seq->s", wq * self.vol, (uh - ex) ** 2).sqrt()
         return err if species is None else err[species]
+
+
+def sdirk_tableau(order: int):
+    """Butcher tableau (A, b, c) of an L-stable, stiffly accurate (b = last row
+    of A) singly diagonally implicit Runge-Kutta scheme of the given order, for
+    the DIRK integrator of Section 3.2 (the paper names only the orders):
+      order 2: Alexander's two-stage scheme, gamma = 1 - 1/sqrt(2);
+      order 3: Alexander's three-stage scheme, gamma the root in (1/6, 1/2) of
+               x^3 - 3x^2 + 3x/2 - 1/6, c = (gamma, (1+gamma)/2, 1);
+      order 4: the five-stage scheme of Hairer and Wanner with gamma = 1/4.
+    Floats (float64); the order conditions are checked in the pins."""
+    if order == 2:
+        g = 1.0 - 1.0 / math.sqrt(2.0)
+        A = [[g, 0.0], [1.0 - g, g]]
+        c = [g, 1.0]
+    elif order == 3:
+        g = 0.4358665215
+        for _ in range(50):     # Newton on the cubic
+            g -= (g ** 3 - 3 * g ** 2 + 1.5 * g - 1.0 / 6.0) / (3 * g ** 2 - 6 * g + 1.5)
+        b1 = -(6 * g * g - 16 * g + 1) / 4.0
+        b2 = (6 * g * g - 20 * g + 5) / 4.0
+        A = [[g, 0.0, 0.0], [(1 - g) / 2.0, g, 0.0], [b1, b2, g]]
+        c = [g, (1 + g) / 2.0, 1.0]
+    elif order == 4:
+        A = [[1 / 4, 0, 0, 0, 0],
+             [1 / 2, 1 / 4, 0, 0, 0],
+             [17 / 50, -1 / 25, 1 / 4, 0, 0],
+             [371 / 1360, -137 / 2720, 15 / 544, 1 / 4, 0],
+             [25 / 24, -49 / 48, 125 / 16, -85 / 12, 1 / 4]]
+        c = [1 / 4, 3 / 4, 11 / 20, 1 / 2, 1.0]
+    else:
+        raise ValueError("SDIRK order must be 2, 3 or 4")
+    return A, list(A[-1]), c
 
 
 def diffusion_only_coeffs(a=1.0) -> dict:
