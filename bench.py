@@ -189,6 +189,44 @@ def bench_adjoint(steps=200, ckpt=20):
             "adjoint_over_apply": round(us_t / us_a, 3)}
 
 
+def bench_implicit(ratio=20.0, order=3):
+    """256^2 Q2: one implicit SDIRK step (Jacobian-free Newton-GMRES) of ratio x the
+    explicit CFL step against the ratio explicit SSP-RK3 steps that cover the same
+    interval (the paper's integrator against the fused explicit one)."""
+    import time
+
+    import torch
+
+    from paper_1403_1157_amd import inputs
+    from paper_1403_1157_amd.cdg2 import Operator
+
+    n = (256, 256)
+    U0 = torch.from_numpy(inputs.initial_modes(2, n, 2, (1,))).cuda()
+    op = Operator(2, n, 2, inputs.base_coeffs())
+    dt = op.max_dt(U0, 0.9)
+    kw = dict(order=order, max_newton=10, krylov_dim=30, newton_rtol=1e-8, krylov_rtol=1e-2)
+    X = U0.clone()
+    op.dirk_step(X, ratio * dt, **kw)            # warm-up (allocates the workspace)
+    X = U0.clone()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st = op.dirk_step(X, ratio * dt, **kw)
+    torch.cuda.synchronize()
+    ms_imp = (time.perf_counter() - t) * 1e3
+    nsteps = int(round(ratio))
+    Y = U0.clone()
+    ms_exp = time_ms(lambda: op.rk_step(Y, dt, nsteps))
+    op.sync()
+    Z = U0.clone()
+    op.rk_step(Z, dt * ratio / nsteps, nsteps)
+    op.sync()
+    diff = float((X - Z).abs().max())
+    return {"workload": f"256x256 Q2, SDIRK{order}, dt = {ratio:g} x the explicit CFL step",
+            "ms_implicit_step": round(ms_imp, 3), "newton_iters": st["newton_iters"],
+            "krylov_iters": st["krylov_iters"], "ms_explicit_same_interval": round(ms_exp, 3),
+            "implicit_over_explicit": round(ms_imp / ms_exp, 3), "max_abs_diff_vs_explicit": diff}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,7 +235,7 @@ def main():
     ap.add_argument("--workload", default="3d-q2-64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched and adjoint measurements")
+                    help="skip the batched, adjoint and implicit measurements")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM "
                          "byte counters of a profiler run) and exit")
@@ -288,6 +326,7 @@ def main():
     if not args.no_extras:
         line["batched"] = bench_batched()
         line["adjoint"] = bench_adjoint()
+        line["implicit"] = bench_implicit()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(dim, n, p, key, dof)
     print(json.dumps(line), flush=True)

@@ -15,8 +15,9 @@
  * Gauss-Legendre points per direction, local Lax-Friedrichs convective flux,
  * CDG2 diffusion flux 2 chi_e (A r_e([[U]]))|_{K^-_e} with lift factor
  * chi_e = N/2 (2 for quads, 3 for hexes) and K^-_e the low-coordinate
- * neighbour of each face.  Time (Section 3.2 replaced by an explicit method):
- * f(U) = M^{-1} L_h(U), advanced by SSP-RK3 in Shu-Osher form.
+ * neighbour of each face.  Time: f(U) = M^{-1} L_h(U) (Section 3.2), advanced by
+ * SSP-RK3 in Shu-Osher form (cdg2_rk_step, the fused explicit path) or by the
+ * implicit DIRK integrator of Section 3.2 (cdg2_dirk_step).
  *
  * DOF layout (all state buffers): U[s][e][m], s = species in the order above,
  * e = ix + nx (iy + ny iz), m = i + (p+1) (j + (p+1) k) (x mode fastest);
@@ -51,7 +52,8 @@ enum {
   CDG2_ENOMEM = -2,     /* device allocation failed */
   CDG2_EHIP = -3,       /* HIP runtime error (message in cdg2_last_error) */
   CDG2_ENONFINITE = -4, /* a NaN/Inf was written to a state buffer */
-  CDG2_EDOMAIN = -5     /* c + chi^th <= 0 met in a chemotactic sensitivity */
+  CDG2_EDOMAIN = -5,    /* c + chi^th <= 0 met in a chemotactic sensitivity */
+  CDG2_ENOCONV = -6     /* the implicit integrator's Newton iteration did not converge */
 };
 
 enum { CDG2_FP64 = 0, CDG2_FP32 = 1 };
@@ -134,6 +136,46 @@ int cdg2_sync(cdg2_handle* h);
 
 /* Spectral constant rho_hat used by cdg2_max_dt (host-computed at create). */
 double cdg2_rho_hat(const cdg2_handle* h);
+
+/* Controls of the implicit integrator (cdg2_dirk_step). */
+typedef struct {
+  int order;            /* SDIRK order: 2, 3 or 4 */
+  int max_newton;       /* Newton steps per stage, >= 1 */
+  int krylov_dim;       /* GMRES iterations per Newton step, 1..64 */
+  double newton_rtol;   /* stage solved when ||G|| <= newton_rtol (||X|| + dt a_ii ||f(X)||) */
+  double krylov_rtol;   /* GMRES stops when its residual <= krylov_rtol ||G|| */
+} cdg2_implicit_opts;
+
+typedef struct {
+  int newton_iters;     /* Newton steps over all stages */
+  int krylov_iters;     /* GMRES iterations over all Newton steps */
+  int converged;        /* 1 when every stage met newton_rtol */
+  int pad;
+  double max_residual;  /* largest final ||G|| / (||X|| + dt a_ii ||f(X)||) over the stages */
+} cdg2_implicit_stats;
+
+/* One implicit step of size dt (Section 3.2: a DIRK method of order 2, 3 or 4
+ * whose stages are solved by a Jacobian-free Newton-Krylov method with GMRES on
+ * the matrix-free operator).  The schemes are L-stable, stiffly accurate SDIRK
+ * methods: order 2 Alexander's two-stage scheme (gamma = 1 - 1/sqrt(2)), order 3
+ * Alexander's three-stage scheme (gamma = 0.43586652150845899942), order 4 the
+ * five-stage scheme of Hairer and Wanner (gamma = 1/4).  For each stage i the
+ * stage value X solves G(X) = X - dt a_ii f(X) - rhs_i = 0 with
+ * rhs_i = U^n + dt sum_{j<i} a_ij K_j; each Newton step solves
+ * (I - dt a_ii J(X)) d = -G by GMRES (no preconditioner, classical Gram-Schmidt
+ * applied twice, Givens rotations) with the Jacobian-vector product
+ * J v = (f(X + eps v) - f(X)) / eps, eps = sqrt(DBL_EPSILON) (1 + ||X||) for
+ * ||v|| = 1.  K_i = (X - rhs_i) / (dt a_ii) and U^{n+1} = U^n + dt sum b_i K_i.
+ * Norms are 2-norms over all entries, reduced in a fixed order (deterministic).
+ * U: device buffer (FP64 handles only), updated in place on success and left
+ * unchanged otherwise.  opts: NULL for defaults (order 3, max_newton 10,
+ * krylov_dim 30, newton_rtol 1e-10, krylov_rtol 1e-3).  stats: NULL or filled.
+ * Returns CDG2_ENOCONV when a stage misses newton_rtol within max_newton steps.
+ * The call waits for the device (the Krylov scalars live on the host); the
+ * library allocates its workspace ((krylov_dim + 13) state vectors) on first
+ * use and keeps it until cdg2_destroy. */
+int cdg2_dirk_step(cdg2_handle* h, void* U, double dt, const cdg2_implicit_opts* opts,
+                   cdg2_implicit_stats* stats);
 
 /* Adjoint of the operator (the transposed Jacobian J = d f / d U of f = M^{-1}
  * L_h, Sections 3.1-3.2): JTw = J(U)^T w.  U, w, JTw: device buffers of

@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcdg2.so")
 
 CDG2_OK, CDG2_EINVAL, CDG2_ENOMEM, CDG2_EHIP, CDG2_ENONFINITE, CDG2_EDOMAIN = 0, -1, -2, -3, -4, -5
+CDG2_ENOCONV = -6
 CDG2_FP64, CDG2_FP32 = 0, 1
 CDG2_LLF_ALL, CDG2_LLF_CELLS = 0, 1
 
@@ -40,6 +41,16 @@ class cdg2_config(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("order", ctypes.c_int),
                 ("precision", ctypes.c_int), ("wall_axis", ctypes.c_int),
                 ("llf_mode", ctypes.c_int), ("gamma1_in", _d * 2), ("coeffs", cdg2_coeffs)]
+
+
+class cdg2_implicit_opts(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int), ("max_newton", ctypes.c_int), ("krylov_dim", ctypes.c_int),
+                ("newton_rtol", _d), ("krylov_rtol", _d)]
+
+
+class cdg2_implicit_stats(ctypes.Structure):
+    _fields_ = [("newton_iters", ctypes.c_int), ("krylov_iters", ctypes.c_int),
+                ("converged", ctypes.c_int), ("pad", ctypes.c_int), ("max_residual", _d)]
 
 
 class CDG2Error(RuntimeError):
@@ -75,6 +86,8 @@ def lib():
     L.cdg2_apply_adjoint.argtypes = [P, P, P, P, ctypes.POINTER(_d)]
     L.cdg2_rk_step_adjoint.argtypes = [P, P, P, P, _d, ctypes.POINTER(_d)]
     L.cdg2_rk_adjoint_segment.argtypes = [P, P, ctypes.c_int, _d, P, ctypes.POINTER(_d)]
+    L.cdg2_dirk_step.argtypes = [P, P, _d, ctypes.POINTER(cdg2_implicit_opts),
+                                 ctypes.POINTER(cdg2_implicit_stats)]
     L.cdg2_batch_create.argtypes = [ctypes.POINTER(cdg2_config), ctypes.c_int, ctypes.POINTER(P)]
     L.cdg2_batch_destroy.argtypes = [P]
     L.cdg2_batch_set_stream.argtypes = [P, P]
@@ -90,6 +103,7 @@ def lib():
     for name in ("cdg2_create", "cdg2_destroy", "cdg2_set_stream", "cdg2_set_coeffs",
                  "cdg2_apply_operator", "cdg2_rk_step", "cdg2_max_dt", "cdg2_sync",
                  "cdg2_apply_adjoint", "cdg2_rk_step_adjoint", "cdg2_rk_adjoint_segment",
+                 "cdg2_dirk_step",
                  "cdg2_batch_create",
                  "cdg2_batch_destroy", "cdg2_batch_set_stream", "cdg2_batch_set_schedule",
                  "cdg2_batch_rk", "cdg2_batch_sync"):
@@ -195,6 +209,20 @@ def cdg2_rk_adjoint_segment(h, U_start_ptr: int, nsteps: int, dt: float, lam_ptr
                                          ctypes.c_void_p(lam_ptr),
                                          ctypes.cast(ctypes.c_void_p(dtheta_acc_ptr or None),
                                                      ctypes.POINTER(_d))))
+
+
+def cdg2_dirk_step(h, U_ptr: int, dt: float, opts: cdg2_implicit_opts | None = None) -> dict:
+    """One implicit SDIRK step in place; returns the solver statistics."""
+    st = cdg2_implicit_stats()
+    rc = lib().cdg2_dirk_step(h, ctypes.c_void_p(U_ptr), float(dt),
+                              ctypes.byref(opts) if opts is not None else None, ctypes.byref(st))
+    stats = {"newton_iters": st.newton_iters, "krylov_iters": st.krylov_iters,
+             "converged": bool(st.converged), "max_residual": st.max_residual}
+    if rc != CDG2_OK:
+        err = CDG2Error(rc, lib().cdg2_last_error().decode())
+        err.stats = stats
+        raise err
+    return stats
 
 
 def cdg2_batch_create(cfgs) -> ctypes.c_void_p:
@@ -304,6 +332,15 @@ class Operator:
             ptr = dtheta_acc.data_ptr()
         cdg2_rk_step_adjoint(self.h, self._arg(U_n), self._arg(lam_np1), self._arg(lam_n), dt, ptr)
         return lam_n
+
+    def dirk_step(self, U: torch.Tensor, dt: float, order: int = 3, max_newton: int = 10,
+                  krylov_dim: int = 30, newton_rtol: float = 1e-10, krylov_rtol: float = 1e-3) -> dict:
+        """One implicit SDIRK step (orders 2-4, Jacobian-free Newton-GMRES) in place;
+        returns the solver statistics (raises CDG2Error, code CDG2_ENOCONV, if a
+        stage does not converge; U is then unchanged)."""
+        self._stream()
+        opts = cdg2_implicit_opts(order, max_newton, krylov_dim, newton_rtol, krylov_rtol)
+        return cdg2_dirk_step(self.h, self._arg(U), dt, opts)
 
     def rk_adjoint_segment(self, U_start, nsteps, dt, lam, dtheta_acc=None):
         """Adjoint of nsteps steps from U_start: lam (in place) goes from dL/dU at the

@@ -15,6 +15,7 @@
 #include "adj_kernel.hpp"
 #include "batch_kernel.hpp"
 #include "es_kernel.hpp"
+#include "vec_kernel.hpp"
 #include "tables.cpp"
 
 using namespace cdg2;
@@ -58,6 +59,13 @@ struct cdg2_handle {
   int nblk_adj = 0;
   void* seg = nullptr;                 // adjoint segment workspace (3 states per step)
   size_t seg_cap = 0;                  // its capacity in states
+  double* imp = nullptr;               // implicit integrator workspace (imp_nvec states)
+  int imp_nvec = 0;
+  double* imp_part = nullptr;          // dot-product partials
+  double* imp_dres = nullptr;          // dot-product results (device)
+  double* imp_dcoef = nullptr;         // combination coefficients (device)
+  double* imp_hres = nullptr;          // pinned host copies
+  double* imp_hcoef = nullptr;
   hipStream_t stream = nullptr;
   double rho_hat = 0.0;
 };
@@ -253,6 +261,134 @@ bool overlap(const void* a, const void* b, size_t bytes) {
   return x < y + bytes && y < x + bytes;
 }
 
+// [a, a + na) and [b, b + nb) intersect
+bool overlap2(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + nb && y < x + na;
+}
+
+
+// ---- implicit SDIRK integrator: Jacobian-free Newton-Krylov (GMRES) ---------------
+
+constexpr int IMP_KMAX = 64;   // largest Krylov dimension
+constexpr int IMP_FIXED = 13;  // 5 stage derivatives + rhs, X, F, G, T, Fe, W, out
+
+// Butcher tableau of the L-stable, stiffly accurate SDIRK scheme of an order.
+struct Sdirk {
+  int s = 0;
+  double A[5][5] = {};
+  double b[5] = {};
+};
+
+bool sdirk(int order, Sdirk* t) {
+  *t = Sdirk();
+  if (order == 2) {
+    const double g = 1.0 - 1.0 / std::sqrt(2.0);
+    t->s = 2;
+    t->A[0][0] = g;
+    t->A[1][0] = 1.0 - g;
+    t->A[1][1] = g;
+  } else if (order == 3) {
+    // gamma: root in (1/6, 1/2) of x^3 - 3x^2 + 3x/2 - 1/6 (Newton from 0.44)
+    double g = 0.44;
+    for (int it = 0; it < 60; ++it) g -= (((g - 3.0) * g + 1.5) * g - 1.0 / 6.0) / ((3.0 * g - 6.0) * g + 1.5);
+    t->s = 3;
+    t->A[0][0] = g;
+    t->A[1][0] = 0.5 * (1.0 - g);
+    t->A[1][1] = g;
+    t->A[2][0] = -(6.0 * g * g - 16.0 * g + 1.0) / 4.0;
+    t->A[2][1] = (6.0 * g * g - 20.0 * g + 5.0) / 4.0;
+    t->A[2][2] = g;
+  } else if (order == 4) {
+    const double A[5][5] = {{1.0 / 4, 0, 0, 0, 0},
+                            {1.0 / 2, 1.0 / 4, 0, 0, 0},
+                            {17.0 / 50, -1.0 / 25, 1.0 / 4, 0, 0},
+                            {371.0 / 1360, -137.0 / 2720, 15.0 / 544, 1.0 / 4, 0},
+                            {25.0 / 24, -49.0 / 48, 125.0 / 16, -85.0 / 12, 1.0 / 4}};
+    t->s = 5;
+    std::memcpy(t->A, A, sizeof A);
+  } else {
+    return false;
+  }
+  for (int i = 0; i < t->s; ++i) t->b[i] = t->A[t->s - 1][i];   // stiffly accurate
+  return true;
+}
+
+int ensure_implicit(cdg2_handle* h, int kdim) {
+  const int nvec = IMP_FIXED + kdim + 1;
+  if (h->imp && h->imp_nvec >= nvec) return CDG2_OK;
+  if (h->imp) {
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    (void)hipFree(h->imp);
+    h->imp = nullptr;
+    h->imp_nvec = 0;
+  }
+  if (hipMalloc((void**)&h->imp, (size_t)nvec * h->ndof * sizeof(double)) != hipSuccess)
+    return fail(CDG2_ENOMEM, "hipMalloc of the implicit workspace (%d states) failed", nvec);
+  h->imp_nvec = nvec;
+  if (!h->imp_part) {
+    if (hipMalloc((void**)&h->imp_part, (size_t)DOT_NB * (IMP_KMAX + 2) * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&h->imp_dres, (IMP_KMAX + 2) * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&h->imp_dcoef, (IMP_KMAX + 2) * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void**)&h->imp_hres, (IMP_KMAX + 2) * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h->imp_hcoef, (IMP_KMAX + 2) * sizeof(double), hipHostMallocDefault) != hipSuccess)
+      return fail(CDG2_ENOMEM, "allocation of the implicit reduction buffers failed");
+  }
+  return CDG2_OK;
+}
+
+struct Vec {
+  cdg2_handle* h;
+  size_t n;
+  int grid() const {
+    size_t g = (n + VEC_NT - 1) / VEC_NT;
+    return (int)(g < 4096 ? g : 4096);
+  }
+  hipError_t lc(double* out, const double* x0, double a0, const double* x1 = nullptr, double a1 = 0.0,
+                const double* x2 = nullptr, double a2 = 0.0, const double* x3 = nullptr, double a3 = 0.0) const {
+    hipLaunchKernelGGL(lincomb_kernel, dim3(grid()), dim3(VEC_NT), 0, h->stream, n, out, x0, a0, x1, a1, x2, a2,
+                       x3, a3);
+    return hipGetLastError();
+  }
+  // dots of w with V_0..V_{k-1} (stride n) and, if self, with itself -> out[0..k(+1))
+  hipError_t dots(const double* w, const double* V, int k, int self, double* out) const {
+    const int kk = k + (self ? 1 : 0);
+    hipLaunchKernelGGL(dots_kernel, dim3(DOT_NB, (kk + DOT_W - 1) / DOT_W), dim3(VEC_NT), 0, h->stream, n, w, V, n,
+                       k, self, h->imp_part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(dots_reduce_kernel, dim3(kk), dim3(VEC_NT), 0, h->stream, (const double*)h->imp_part,
+                       h->imp_dres);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(h->imp_hres, h->imp_dres, kk * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return e;
+    std::memcpy(out, h->imp_hres, kk * sizeof(double));
+    return hipSuccess;
+  }
+  double norm_of(const double* x, hipError_t* e) const {
+    double r = 0.0;
+    *e = dots(x, nullptr, 0, 1, &r);
+    return std::sqrt(r);
+  }
+  // w -= scale sum_j c[j] V_j   (c: host values, copied through the pinned buffer;
+  // the previous copy has completed: every dots() waits for the stream)
+  hipError_t maxpy(double* w, const double* V, int k, const double* c, double scale) const {
+    std::memcpy(h->imp_hcoef, c, k * sizeof(double));
+    hipError_t e = hipMemcpyAsync(h->imp_dcoef, h->imp_hcoef, k * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(multi_axpy_kernel, dim3(grid()), dim3(VEC_NT), 0, h->stream, n, w, V, n, k,
+                       (const double*)h->imp_dcoef, scale);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // keep the pinned coefficients alive until the copy has run
+    return hipStreamSynchronize(h->stream);
+  }
+};
+
 }  // namespace
 
 extern "C" {
@@ -308,6 +444,12 @@ int cdg2_destroy(cdg2_handle* h) {
   if (h->part) (void)hipFree(h->part);
   if (h->dth) (void)hipFree(h->dth);
   if (h->seg) (void)hipFree(h->seg);
+  if (h->imp) (void)hipFree(h->imp);
+  if (h->imp_part) (void)hipFree(h->imp_part);
+  if (h->imp_dres) (void)hipFree(h->imp_dres);
+  if (h->imp_dcoef) (void)hipFree(h->imp_dcoef);
+  if (h->imp_hres) (void)hipHostFree(h->imp_hres);
+  if (h->imp_hcoef) (void)hipHostFree(h->imp_hcoef);
   delete h;
   return CDG2_OK;
 }
@@ -452,6 +594,149 @@ int cdg2_rk_adjoint_segment(cdg2_handle* h, const void* U_start, int nsteps, dou
   }
   h->dth = acc_save;
   if (e != hipSuccess) return fail(CDG2_EHIP, "adjoint segment launch: %s", hipGetErrorString(e));
+  return CDG2_OK;
+}
+
+
+int cdg2_dirk_step(cdg2_handle* h, void* U, double dt, const cdg2_implicit_opts* opts,
+                   cdg2_implicit_stats* stats) {
+  if (!h || !U) return fail(CDG2_EINVAL, "NULL argument");
+  if (h->fp32) return fail(CDG2_EINVAL, "the implicit integrator needs a CDG2_FP64 handle");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(CDG2_EINVAL, "dt must be finite and > 0");
+  cdg2_implicit_opts o = {3, 10, 30, 1e-10, 1e-3};
+  if (opts) o = *opts;
+  Sdirk tab;
+  if (!sdirk(o.order, &tab)) return fail(CDG2_EINVAL, "order must be 2, 3 or 4 (got %d)", o.order);
+  if (o.max_newton < 1) return fail(CDG2_EINVAL, "max_newton must be >= 1");
+  if (o.krylov_dim < 1 || o.krylov_dim > IMP_KMAX) return fail(CDG2_EINVAL, "krylov_dim must be in 1..%d", IMP_KMAX);
+  if (!(o.newton_rtol > 0) || !(o.krylov_rtol > 0)) return fail(CDG2_EINVAL, "tolerances must be > 0");
+  int rc = ensure_implicit(h, o.krylov_dim);
+  if (rc) return rc;
+  const size_t n = h->ndof;
+  if (overlap2(U, n * sizeof(double), h->imp, (size_t)h->imp_nvec * n * sizeof(double)))
+    return fail(CDG2_EINVAL, "U overlaps the implicit workspace");
+  double* W0 = h->imp;
+  auto vec = [&](int k) { return W0 + (size_t)k * n; };
+  double* K[5] = {vec(0), vec(1), vec(2), vec(3), vec(4)};
+  double *rhs = vec(5), *X = vec(6), *F = vec(7), *G = vec(8), *T = vec(9), *Fe = vec(10), *Wv = vec(11),
+         *out = vec(12);
+  double* V = vec(IMP_FIXED);
+  const double* Un = (const double*)U;
+  const Vec v{h, n};
+  const int m = o.krylov_dim;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), h1(m + 2), h2(m + 2);
+  auto Hij = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+  cdg2_implicit_stats st = {0, 0, 1, 0, 0.0};
+  hipError_t e = hipSuccess;
+#define IMP_TRY(expr)                                                       \
+  do {                                                                      \
+    e = (expr);                                                             \
+    if (e != hipSuccess) return fail(CDG2_EHIP, "implicit step: %s", hipGetErrorString(e)); \
+  } while (0)
+  for (int i = 0; i < tab.s; ++i) {
+    // rhs_i = U^n + dt sum_{j<i} a_ij K_j (in groups of three terms)
+    IMP_TRY(v.lc(rhs, Un, 1.0));
+    for (int j0 = 0; j0 < i; j0 += 3) {
+      const int j1 = j0 + 1 < i ? j0 + 1 : -1, j2 = j0 + 2 < i ? j0 + 2 : -1;
+      IMP_TRY(v.lc(rhs, rhs, 1.0, K[j0], dt * tab.A[i][j0], j1 >= 0 ? K[j1] : nullptr,
+                   j1 >= 0 ? dt * tab.A[i][j1] : 0.0, j2 >= 0 ? K[j2] : nullptr, j2 >= 0 ? dt * tab.A[i][j2] : 0.0));
+    }
+    const double dg = dt * tab.A[i][i];
+    IMP_TRY(v.lc(X, rhs, 1.0));
+    bool ok = false;
+    double rel = 0.0;
+    for (int it = 0; it <= o.max_newton; ++it) {
+      IMP_TRY(run_op(h, X, nullptr, F, 0.0, 0.0, 1.0, 0));
+      IMP_TRY(v.lc(G, X, 1.0, F, -dg, rhs, -1.0));
+      const double nG = v.norm_of(G, &e);
+      if (e != hipSuccess) return fail(CDG2_EHIP, "implicit step: %s", hipGetErrorString(e));
+      const double nX = v.norm_of(X, &e);
+      if (e != hipSuccess) return fail(CDG2_EHIP, "implicit step: %s", hipGetErrorString(e));
+      const double nF = v.norm_of(F, &e);
+      if (e != hipSuccess) return fail(CDG2_EHIP, "implicit step: %s", hipGetErrorString(e));
+      if (!std::isfinite(nG) || !std::isfinite(nX) || !std::isfinite(nF))
+        return fail(CDG2_ENONFINITE, "non-finite value in the implicit stage iteration");
+      const double scale = nX + dg * nF;
+      rel = scale > 0 ? nG / scale : nG;
+      if (nG <= o.newton_rtol * scale) {
+        ok = true;
+        break;
+      }
+      if (it == o.max_newton) break;
+      ++st.newton_iters;
+      // GMRES on (I - dg J(X)) d = -G from d = 0: V_0 = -G / ||G||
+      const double beta = nG;
+      IMP_TRY(v.lc(V, G, -1.0 / beta));
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      const double eps = std::sqrt(2.220446049250313e-16) * (1.0 + nX);
+      int jend = 0;
+      for (int j = 0; j < m; ++j) {
+        double* Vj = V + (size_t)j * n;
+        double* Vn = V + (size_t)(j + 1) * n;
+        // W = V_j - dg (f(X + eps V_j) - f(X)) / eps
+        IMP_TRY(v.lc(T, X, 1.0, Vj, eps));
+        IMP_TRY(run_op(h, T, nullptr, Fe, 0.0, 0.0, 1.0, 0));
+        IMP_TRY(v.lc(Wv, Vj, 1.0, Fe, -dg / eps, F, dg / eps));
+        // classical Gram-Schmidt, twice; the second pass also gives ||W||^2
+        IMP_TRY(v.dots(Wv, V, j + 1, 0, h1.data()));
+        IMP_TRY(v.maxpy(Wv, V, j + 1, h1.data(), 1.0));
+        IMP_TRY(v.dots(Wv, V, j + 1, 1, h2.data()));
+        IMP_TRY(v.maxpy(Wv, V, j + 1, h2.data(), 1.0));
+        double hn2 = h2[j + 1];
+        for (int q = 0; q <= j; ++q) {
+          hn2 -= h2[q] * h2[q];
+          Hij(q, j) = h1[q] + h2[q];
+        }
+        const double hn = hn2 > 0 ? std::sqrt(hn2) : 0.0;
+        Hij(j + 1, j) = hn;
+        if (hn > 0) IMP_TRY(v.lc(Vn, Wv, 1.0 / hn));
+        // Givens rotations: previous ones on column j, then a new one
+        for (int q = 0; q < j; ++q) {
+          const double a = Hij(q, j), b = Hij(q + 1, j);
+          Hij(q, j) = cs[q] * a + sn[q] * b;
+          Hij(q + 1, j) = -sn[q] * a + cs[q] * b;
+        }
+        const double r = std::hypot(Hij(j, j), Hij(j + 1, j));
+        cs[j] = r > 0 ? Hij(j, j) / r : 1.0;
+        sn[j] = r > 0 ? Hij(j + 1, j) / r : 0.0;
+        Hij(j, j) = r;
+        Hij(j + 1, j) = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        ++st.krylov_iters;
+        jend = j + 1;
+        if (std::fabs(g[j + 1]) <= o.krylov_rtol * beta || hn == 0) break;
+      }
+      // y = H^{-1} g (upper triangular), X += sum y_q V_q
+      for (int q = jend - 1; q >= 0; --q) {
+        double sacc = g[q];
+        for (int c2 = q + 1; c2 < jend; ++c2) sacc -= Hij(q, c2) * y[c2];
+        y[q] = Hij(q, q) != 0 ? sacc / Hij(q, q) : 0.0;
+      }
+      IMP_TRY(v.maxpy(X, V, jend, y.data(), -1.0));
+    }
+    st.max_residual = std::fmax(st.max_residual, rel);
+    if (!ok) {
+      st.converged = 0;
+      if (stats) *stats = st;
+      return fail(CDG2_ENOCONV, "implicit stage %d: Newton residual %.3e > %.3e after %d steps", i, rel,
+                  o.newton_rtol, o.max_newton);
+    }
+    // K_i = (X - rhs_i) / (dt a_ii)
+    IMP_TRY(v.lc(K[i], X, 1.0 / dg, rhs, -1.0 / dg));
+  }
+  // U^{n+1} = U^n + dt sum b_i K_i
+  IMP_TRY(v.lc(out, Un, 1.0));
+  for (int j0 = 0; j0 < tab.s; j0 += 3) {
+    const int j1 = j0 + 1 < tab.s ? j0 + 1 : -1, j2 = j0 + 2 < tab.s ? j0 + 2 : -1;
+    IMP_TRY(v.lc(out, out, 1.0, K[j0], dt * tab.b[j0], j1 >= 0 ? K[j1] : nullptr, j1 >= 0 ? dt * tab.b[j1] : 0.0,
+                 j2 >= 0 ? K[j2] : nullptr, j2 >= 0 ? dt * tab.b[j2] : 0.0));
+  }
+  IMP_TRY(hipMemcpyAsync(U, out, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  IMP_TRY(hipStreamSynchronize(h->stream));
+#undef IMP_TRY
+  if (stats) *stats = st;
   return CDG2_OK;
 }
 

@@ -40,6 +40,11 @@ def test_struct_layout_matches_header():
     # 26 doubles of coefficients; config = 6 ints + pad to 8 + 2 doubles + coeffs
     assert ctypes.sizeof(B.cdg2_coeffs) == 26 * 8
     assert B.cdg2_config.coeffs.offset == ctypes.sizeof(ctypes.c_int) * 8 + 16
+    # implicit controls: 3 ints + pad + 2 doubles; statistics: 4 ints + 1 double
+    assert ctypes.sizeof(B.cdg2_implicit_opts) == 32
+    assert B.cdg2_implicit_opts.newton_rtol.offset == 16
+    assert ctypes.sizeof(B.cdg2_implicit_stats) == 24
+    assert B.cdg2_implicit_stats.max_residual.offset == 16
 
 
 @pytest.mark.parametrize("field,value", [
@@ -83,5 +88,6 @@ def test_null_arguments_rejected():
     assert L.cdg2_rk_step(None, None, 0.1, 1) == B.CDG2_EINVAL
     assert L.cdg2_rk_step_adjoint(None, None, None, None, 0.1, None) == B.CDG2_EINVAL
     assert L.cdg2_rk_adjoint_segment(None, None, 1, 0.1, None, None) == B.CDG2_EINVAL
+    assert L.cdg2_dirk_step(None, None, 0.1, None, None) == B.CDG2_EINVAL
     assert L.cdg2_destroy(None) == B.CDG2_OK
     assert L.cdg2_num_dofs(None) == 0
