@@ -163,7 +163,7 @@ typedef struct {
  * stage value X solves G(X) = X - dt a_ii f(X) - rhs_i = 0 with
  * rhs_i = U^n + dt sum_{j<i} a_ij K_j; each Newton step solves
  * (I - dt a_ii J(X)) d = -G by GMRES (no preconditioner, classical Gram-Schmidt
- * applied twice, Givens rotations) with the Jacobian-vector product
+ * with a second pass when the first cancels most of the vector, Givens rotations) with the Jacobian-vector product
  * J v = (f(X + eps v) - f(X)) / eps, eps = sqrt(DBL_EPSILON) (1 + ||X||) for
  * ||v|| = 1.  K_i = (X - rhs_i) / (dt a_ii) and U^{n+1} = U^n + dt sum b_i K_i.
  * Norms are 2-norms over all entries, reduced in a fixed order (deterministic).

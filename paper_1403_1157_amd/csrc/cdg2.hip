@@ -329,9 +329,9 @@ int ensure_implicit(cdg2_handle* h, int kdim) {
   h->imp_nvec = nvec;
   if (!h->imp_part) {
     if (hipMalloc((void**)&h->imp_part, (size_t)DOT_NB * (IMP_KMAX + 2) * sizeof(double)) != hipSuccess ||
-        hipMalloc((void**)&h->imp_dres, (IMP_KMAX + 2) * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&h->imp_dres, 2 * (IMP_KMAX + 2) * sizeof(double)) != hipSuccess ||
         hipMalloc((void**)&h->imp_dcoef, (IMP_KMAX + 2) * sizeof(double)) != hipSuccess ||
-        hipHostMalloc((void**)&h->imp_hres, (IMP_KMAX + 2) * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h->imp_hres, 2 * (IMP_KMAX + 2) * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&h->imp_hcoef, (IMP_KMAX + 2) * sizeof(double), hipHostMallocDefault) != hipSuccess)
       return fail(CDG2_ENOMEM, "allocation of the implicit reduction buffers failed");
   }
@@ -367,6 +367,31 @@ struct Vec {
     e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return e;
     std::memcpy(out, h->imp_hres, kk * sizeof(double));
+    return hipSuccess;
+  }
+  // the same dots left on the device at h->imp_dres + off (no host wait)
+  hipError_t dots_dev(const double* w, const double* V, int k, int self, int off) const {
+    const int kk = k + (self ? 1 : 0);
+    hipLaunchKernelGGL(dots_kernel, dim3(DOT_NB, (kk + DOT_W - 1) / DOT_W), dim3(VEC_NT), 0, h->stream, n, w, V, n,
+                       k, self, h->imp_part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(dots_reduce_kernel, dim3(kk), dim3(VEC_NT), 0, h->stream, (const double*)h->imp_part,
+                       h->imp_dres + off);
+    return hipGetLastError();
+  }
+  // w -= scale sum_j c[j] V_j with c on the device
+  hipError_t maxpy_dev(double* w, const double* V, int k, const double* c, double scale) const {
+    hipLaunchKernelGGL(multi_axpy_kernel, dim3(grid()), dim3(VEC_NT), 0, h->stream, n, w, V, n, k, c, scale);
+    return hipGetLastError();
+  }
+  // copy cnt device results from offset 0 to the host (waits for the stream)
+  hipError_t fetch(int cnt, double* out) const {
+    hipError_t e = hipMemcpyAsync(h->imp_hres, h->imp_dres, cnt * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return e;
+    std::memcpy(out, h->imp_hres, cnt * sizeof(double));
     return hipSuccess;
   }
   double norm_of(const double* x, hipError_t* e) const {
@@ -678,15 +703,29 @@ int cdg2_dirk_step(cdg2_handle* h, void* U, double dt, const cdg2_implicit_opts*
         IMP_TRY(v.lc(T, X, 1.0, Vj, eps));
         IMP_TRY(run_op(h, T, nullptr, Fe, 0.0, 0.0, 1.0, 0));
         IMP_TRY(v.lc(Wv, Vj, 1.0, Fe, -dg / eps, F, dg / eps));
-        // classical Gram-Schmidt, twice; the second pass also gives ||W||^2
-        IMP_TRY(v.dots(Wv, V, j + 1, 0, h1.data()));
-        IMP_TRY(v.maxpy(Wv, V, j + 1, h1.data(), 1.0));
-        IMP_TRY(v.dots(Wv, V, j + 1, 1, h2.data()));
-        IMP_TRY(v.maxpy(Wv, V, j + 1, h2.data(), 1.0));
-        double hn2 = h2[j + 1];
+        // classical Gram-Schmidt with the coefficients kept on the device; a
+        // second pass only when the first removed most of W (the "twice is
+        // enough" test ||W'|| < 0.7 ||W||); norms by Pythagoras from the dots
+        const int o2 = IMP_KMAX + 2;
+        IMP_TRY(v.dots_dev(Wv, V, j + 1, 1, 0));
+        IMP_TRY(v.maxpy_dev(Wv, V, j + 1, h->imp_dres, 1.0));
+        IMP_TRY(v.fetch(j + 2, h1.data()));
+        double w2 = h1[j + 1], hn2 = w2;
         for (int q = 0; q <= j; ++q) {
-          hn2 -= h2[q] * h2[q];
-          Hij(q, j) = h1[q] + h2[q];
+          hn2 -= h1[q] * h1[q];
+          Hij(q, j) = h1[q];
+        }
+        if (!(hn2 >= 0.49 * w2)) {
+          IMP_TRY(v.dots_dev(Wv, V, j + 1, 1, o2));
+          IMP_TRY(v.maxpy_dev(Wv, V, j + 1, h->imp_dres + o2, 1.0));
+          std::vector<double> both(2 * o2);
+          IMP_TRY(v.fetch(2 * o2, both.data()));
+          for (int q = 0; q <= j + 1; ++q) h2[q] = both[o2 + q];
+          hn2 = h2[j + 1];
+          for (int q = 0; q <= j; ++q) {
+            hn2 -= h2[q] * h2[q];
+            Hij(q, j) += h2[q];
+          }
         }
         const double hn = hn2 > 0 ? std::sqrt(hn2) : 0.0;
         Hij(j + 1, j) = hn;
