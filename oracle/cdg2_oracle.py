@@ -78,6 +78,8 @@ class Config:
     gamma1_in: tuple = (0.0, 1.0)
     llf_mode: str = "all"        # "all" | "cells"
     coeffs: dict = field(default_factory=dict)
+    diff_flux: str = "cdg2"      # "cdg2" | "br2" | "ip" | "bo" (diffusion flux, Section 3.1)
+    flux_eta: float = 0.0        # penalty of br2 / ip; 0: default (br2: N = 2d, ip: 2d)
 
     def resolved_wall(self) -> int:
         return self.dim - 1 if self.wall_axis == -2 else self.wall_axis
@@ -204,6 +206,8 @@ class Oracle:
         self.nm = (p + 1) ** d
         self.wall = cfg.resolved_wall()
         self.chi_e = float(d)             # N/2 with N = 2d faces per cell
+        assert cfg.diff_flux in ("cdg2", "br2", "ip", "bo")
+        self.flux_eta = float(cfg.flux_eta) if cfg.flux_eta > 0 else float(2 * d)
         self.vol = math.prod(self.h)
         x1, w1 = gauss_legendre01(self.q)
         self.x1, self.w1 = x1, w1
@@ -359,12 +363,28 @@ class Oracle:
             diss = torch.cat([0.5 * lam[None] * jump[:2], torch.zeros_like(jump[2:])])
             Fhat = Fn + diss
         # consistency average {A grad U}.n^-
-        avg = 0.5 * a.reshape(6, *([1] * (jump.dim() - 1))) * (dnm + dnp)
-        # CDG2 lifting on K^- (general route: mass solve on K^-)
-        rn = self.lift_trace(jump, ax)                               # r_e . n^-
-        Ahat = 2.0 * self.chi_e * a.reshape(6, *([1] * (jump.dim() - 1))) * rn
+        ab = a.reshape(6, *([1] * (jump.dim() - 1)))
+        avg = 0.5 * ab * (dnm + dnp)
+        # diffusion stabilisation (the comparison fluxes of Section 4 share the
+        # consistency term; they differ in the stabilisation and the symmetry term)
+        flux = self.cfg.diff_flux
+        if flux == "cdg2":
+            # CDG2: lifting on K^- (general route: mass solve on K^-)
+            Ahat = 2.0 * self.chi_e * ab * self.lift_trace(jump, ax)
+        elif flux == "br2":
+            # BR2: eta times the average of the liftings on K^- and K^+
+            rbar = 0.5 * (self.lift_trace(jump, ax) + self.lift_trace_plus(jump, ax))
+            Ahat = self.flux_eta * ab * rbar
+        elif flux == "ip":
+            # interior penalty: eta a (p+1)^2 / h [[U]]
+            Ahat = -self.flux_eta * ab * (self.p + 1) ** 2 / self.h[ax] * jump
+        else:
+            # Baumann-Oden: no stabilisation, symmetry term with the opposite sign
+            Ahat = torch.zeros_like(jump)
         gflux = avg - Fhat + Ahat                                    # multiplies (phi^- - phi^+)
-        sym = 0.5 * a.reshape(6, *([1] * (jump.dim() - 1))) * jump    # multiplies dn phi (both sides)
+        sym = 0.5 * ab * jump                                        # multiplies dn phi (both sides)
+        if flux == "bo":
+            sym = -sym
         wf = F["wf"]
         # test functions on K- (trace at xi_ax = 1) and on K+ (xi_ax = 0)
         Rm = torch.einsum("t,s...t,tm->s...m", wf, gflux, F["PhiHi"]) \
@@ -396,6 +416,15 @@ class Oracle:
         shp = b.shape
         rho = torch.cholesky_solve(b.reshape(-1, self.nm).T, self.Mchol).T.reshape(shp)
         return torch.einsum("s...m,tm->s...t", rho, F["PhiHi"])
+
+    def lift_trace_plus(self, jump: torch.Tensor, ax: int) -> torch.Tensor:
+        """n^- component of the lifting r_e([[V]]) restricted to K^+, at the face
+        points: M_{K+} rho = -1/2 n^-_ax int_e (u^- - u^+) phi^{K+}."""
+        F = self.faces[ax]
+        b = -0.5 * torch.einsum("t,s...t,tm->s...m", F["wf"], jump, F["PhiLo"])
+        shp = b.shape
+        rho = torch.cholesky_solve(b.reshape(-1, self.nm).T, self.Mchol).T.reshape(shp)
+        return torch.einsum("s...m,tm->s...t", rho, F["PhiLo"])
 
     def _boundary(self, UG, th, ax):
         """Inflow boundary fluxes of eqs. (7)-(9) on Gamma1 (low end of the wall
