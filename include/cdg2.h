@@ -61,6 +61,18 @@ enum { CDG2_FP64 = 0, CDG2_FP32 = 1 };
 /* LLF dissipation rows: all six species (default) or only n1, n2. */
 enum { CDG2_LLF_ALL = 0, CDG2_LLF_CELLS = 1 };
 
+/* Diffusion flux (Section 3.1; the others are the paper's comparison fluxes of
+ * Section 4).  All share the consistency term {A grad U}:[[phi]]; they differ in
+ * the stabilisation and the sign of the symmetry term {A grad phi}:[[U]]:
+ *   CDG2: 2 chi_e (A r_e([[U]]))|_{K^-}, chi_e = N/2 (N = 2 dim faces per cell);
+ *   BR2:  eta {A r_e([[U]])} (average of the liftings on both neighbours);
+ *   IP:   eta A (p+1)^2 / h [[U]] (symmetric interior penalty);
+ *   BO:   Baumann-Oden: no stabilisation, symmetry term with the opposite sign.
+ * On uniform Cartesian cells the lifting has the same trace from both sides
+ * (-(p+1)^2 / (2h) [[U]]), so BR2 with eta = N and IP with eta = dim coincide
+ * with CDG2.  flux_eta = 0 selects eta = 2 dim for BR2 and IP. */
+enum { CDG2_FLUX_CDG2 = 0, CDG2_FLUX_BR2 = 1, CDG2_FLUX_IP = 2, CDG2_FLUX_BO = 3 };
+
 /* Coefficients of Section 2 (the paper gives symbols only).  The first 21 are
  * the differentiable coefficients in this order: mu1..3, nu1..3 (motilities),
  * chi0_{11,13,21,22}, chith_{11,13,21,22} (tactic sensitivities; 22 is the
@@ -88,6 +100,9 @@ typedef struct {
   int llf_mode;         /* CDG2_LLF_ALL | CDG2_LLF_CELLS */
   double gamma1_in[2];  /* Gamma_{1,in} = [g0, g1] on the first tangential axis */
   cdg2_coeffs coeffs;
+  int diff_flux;        /* CDG2_FLUX_* (0: CDG2) */
+  int reserved;         /* 0 */
+  double flux_eta;      /* penalty parameter of BR2 / IP (>= 0; 0: default) */
 } cdg2_config;
 
 typedef struct cdg2_handle cdg2_handle;
@@ -184,7 +199,9 @@ int cdg2_dirk_step(cdg2_handle* h, void* U, double dt, const cdg2_implicit_opts*
  * for the 21 differentiable coefficients (order of cdg2_coeffs); the call then
  * waits for the device.  Non-smooth points: d|x|/dx = sign(x) (0 at 0), the max
  * of the LLF speed takes the first maximiser, the inflow Heaviside has
- * derivative 0.  Parameter sums are reduced in a fixed order (deterministic). */
+ * derivative 0.  Parameter sums are reduced in a fixed order (deterministic).
+ * Symmetric diffusion fluxes only (CDG2, BR2, IP): CDG2_EINVAL for Baumann-Oden,
+ * as for the other adjoint entry points. */
 int cdg2_apply_adjoint(cdg2_handle* h, const void* U, const void* w, void* JTw, double* dtheta);
 
 /* Discrete adjoint of one SSP-RK3 step of size dt started from U_n: given

@@ -18,6 +18,8 @@ CDG2_OK, CDG2_EINVAL, CDG2_ENOMEM, CDG2_EHIP, CDG2_ENONFINITE, CDG2_EDOMAIN = 0,
 CDG2_ENOCONV = -6
 CDG2_FP64, CDG2_FP32 = 0, 1
 CDG2_LLF_ALL, CDG2_LLF_CELLS = 0, 1
+CDG2_FLUX_CDG2, CDG2_FLUX_BR2, CDG2_FLUX_IP, CDG2_FLUX_BO = 0, 1, 2, 3
+FLUXES = {"cdg2": CDG2_FLUX_CDG2, "br2": CDG2_FLUX_BR2, "ip": CDG2_FLUX_IP, "bo": CDG2_FLUX_BO}
 
 COEFF_NAMES = [
     "mu1", "mu2", "mu3", "nu1", "nu2", "nu3",
@@ -40,7 +42,8 @@ class cdg2_coeffs(ctypes.Structure):
 class cdg2_config(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("order", ctypes.c_int),
                 ("precision", ctypes.c_int), ("wall_axis", ctypes.c_int),
-                ("llf_mode", ctypes.c_int), ("gamma1_in", _d * 2), ("coeffs", cdg2_coeffs)]
+                ("llf_mode", ctypes.c_int), ("gamma1_in", _d * 2), ("coeffs", cdg2_coeffs),
+                ("diff_flux", ctypes.c_int), ("reserved", ctypes.c_int), ("flux_eta", _d)]
 
 
 class cdg2_implicit_opts(ctypes.Structure):
@@ -131,7 +134,7 @@ def make_coeffs(c: dict) -> cdg2_coeffs:
 
 def make_config(dim: int, n, order: int, coeffs: dict, precision: str = "fp64",
                 wall_axis: int | None = None, llf_mode: str = "all",
-                gamma1_in=(0.0, 1.0)) -> cdg2_config:
+                gamma1_in=(0.0, 1.0), diff_flux: str = "cdg2", flux_eta: float = 0.0) -> cdg2_config:
     cfg = cdg2_config()
     cfg.dim = int(dim)
     nn = list(n) + [1] * (3 - len(n))
@@ -142,6 +145,8 @@ def make_config(dim: int, n, order: int, coeffs: dict, precision: str = "fp64",
     cfg.llf_mode = CDG2_LLF_CELLS if llf_mode == "cells" else CDG2_LLF_ALL
     cfg.gamma1_in[:] = [float(gamma1_in[0]), float(gamma1_in[1])]
     cfg.coeffs = make_coeffs(coeffs)
+    cfg.diff_flux = FLUXES[diff_flux]
+    cfg.flux_eta = float(flux_eta)
     return cfg
 
 
@@ -276,11 +281,12 @@ class Operator:
     (6, E, (p+1)^dim) in float64 (or float32 with precision="fp32")."""
 
     def __init__(self, dim, n, order, coeffs, precision="fp64", wall_axis=None,
-                 llf_mode="all", gamma1_in=(0.0, 1.0)):
+                 llf_mode="all", gamma1_in=(0.0, 1.0), diff_flux="cdg2", flux_eta=0.0):
         self.dim, self.order = int(dim), int(order)
         self.n = tuple(int(v) for v in n)[:dim]
         self.dtype = torch.float32 if precision == "fp32" else torch.float64
-        self.cfg = make_config(dim, n, order, coeffs, precision, wall_axis, llf_mode, gamma1_in)
+        self.cfg = make_config(dim, n, order, coeffs, precision, wall_axis, llf_mode, gamma1_in,
+                               diff_flux, flux_eta)
         self.h = cdg2_create(self.cfg)
         self.E = 1
         for v in self.n:

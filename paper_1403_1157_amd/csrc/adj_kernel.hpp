@@ -540,7 +540,7 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
       }
       const T ar = T(g.area[a]);
       const T so = sg ? T(1) : T(-1);
-      const T pen = T(g.chi_e * tb.liftc * g.ih[a]);
+      const T pen = T(g.pen_c * tb.liftc * g.ih[a]);   // symmetric fluxes only (host check)
       T G[NF], H[NF], Gu[NF], Hu[NF];
 #pragma unroll
       for (int J = 0; J < NF; ++J) {

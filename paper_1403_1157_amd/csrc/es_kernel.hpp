@@ -533,14 +533,14 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
       tapply_lo<D, Q, true, T>(gp, gh, Tb0, Tb0);
       const T ar = T(g.area[a]);
       const T so = sg ? T(1) : T(-1);
-      const T pen = T(g.chi_e * tb.liftc * g.ih[a]) * as;
+      const T pen = T(g.pen_c * tb.liftc * g.ih[a]) * as;
       T G[NF], H[NF];
 #pragma unroll
       for (int J = 0; J < NF; ++J) {
         T lin = T(0), hh = T(0);
         if (nb >= 0) {
           lin = so * T(0.5) * as * (duo[J] + dun[J]) - pen * jm[J];
-          hh = T(0.5) * as * jm[J] * so * T(g.ih[a]);
+          hh = T(0.5 * g.sym) * as * jm[J] * so * T(g.ih[a]);
         }
         G[J] = ar * (lin + gh[J]);
         H[J] = ar * hh;

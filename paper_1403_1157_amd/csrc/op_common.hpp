@@ -34,7 +34,8 @@ struct Geo {
   double vol;        // |K|
   double area[3];    // |e| of a face normal to each axis
   double g1in[2];    // Gamma_{1,in} on the first tangential axis
-  double chi_e;      // lift factor N/2
+  double pen_c;      // penalty factor: stabilisation pen_c (p+1)^2 a / h [[u]] (CDG2: chi_e = N/2)
+  double sym;        // sign of the symmetry term {A grad phi}:[[U]] (-1: Baumann-Oden)
 };
 
 __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }

@@ -136,13 +136,14 @@ void build_tables(int p, Tables* t) {
   t->liftc = l;
 }
 
-double spectral_constant_1d(int p, double chi_e) {
-  // Symmetric bilinear form of the 1D periodic CDG2 diffusion operator on N = 8
-  // unit cells: sum_K int u'v' - sum_e ({u'}[v] + {v'}[u]) + pen [u][v].
+double spectral_constant_1d(int p, double pen_c, double sym) {
+  // Bilinear form of the 1D periodic diffusion operator on N = 8 unit cells:
+  // sum_K int u'v' - sum_e ({u'}[v] + sym {v'}[u]) + pen [u][v]; its largest
+  // singular value (the largest eigenvalue when the form is symmetric).
   Tables t;
   build_tables(p, &t);
   const int q = p + 1, N = 8, n = N * q;
-  const double pen = chi_e * t.liftc;
+  const double pen = pen_c * t.liftc;
   std::vector<double> K(n * n, 0.0), V;
   for (int c = 0; c < N; ++c)
     for (int i = 0; i < q; ++i)
@@ -162,7 +163,20 @@ double spectral_constant_1d(int p, double chi_e) {
     }
     for (int a = 0; a < 2 * q; ++a)
       for (int b = 0; b < 2 * q; ++b)
-        K[idx[a] * n + idx[b]] += -av[b] * jv[a] - jv[b] * av[a] + pen * jv[a] * jv[b];
+        K[idx[a] * n + idx[b]] += -av[b] * jv[a] - sym * jv[b] * av[a] + pen * jv[a] * jv[b];
+  }
+  if (sym != 1.0) {   // K^T K
+    std::vector<double> KK((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < n; ++k) acc += K[k * n + i] * K[k * n + j];
+        KK[i * n + j] = acc;
+      }
+    jacobi_eigen(n, KK, V);
+    double mx = 0.0;
+    for (int i = 0; i < n; ++i) mx = std::fmax(mx, KK[i * n + i]);
+    return std::sqrt(mx);
   }
   jacobi_eigen(n, K, V);
   double mx = 0.0;

@@ -40,6 +40,10 @@ def test_struct_layout_matches_header():
     # 26 doubles of coefficients; config = 6 ints + pad to 8 + 2 doubles + coeffs
     assert ctypes.sizeof(B.cdg2_coeffs) == 26 * 8
     assert B.cdg2_config.coeffs.offset == ctypes.sizeof(ctypes.c_int) * 8 + 16
+    # flux selection after the coefficients: 2 ints + 1 double
+    assert B.cdg2_config.diff_flux.offset == B.cdg2_config.coeffs.offset + 26 * 8
+    assert B.cdg2_config.flux_eta.offset == B.cdg2_config.diff_flux.offset + 8
+    assert ctypes.sizeof(B.cdg2_config) == B.cdg2_config.flux_eta.offset + 8
     # implicit controls: 3 ints + pad + 2 doubles; statistics: 4 ints + 1 double
     assert ctypes.sizeof(B.cdg2_implicit_opts) == 32
     assert B.cdg2_implicit_opts.newton_rtol.offset == 16
@@ -50,7 +54,8 @@ def test_struct_layout_matches_header():
 @pytest.mark.parametrize("field,value", [
     ("dim", 4), ("dim", 1), ("order", 0), ("order", 5), ("n0", 1), ("wall_axis", 3),
     ("wall_axis", -2), ("precision", 7), ("llf_mode", 3), ("g1", (0.8, 0.2)),
-    ("nan", None), ("neg_diff", None), ("order3d", 4)])
+    ("nan", None), ("neg_diff", None), ("order3d", 4), ("flux", 4), ("flux", -1), ("eta", -1.0),
+    ("eta", float("inf"))])
 def test_invalid_config_rejected(field, value):
     c = inputs.base_coeffs()
     dim, order = 2, 2
@@ -71,6 +76,10 @@ def test_invalid_config_rejected(field, value):
         cfg.llf_mode = value
     elif field == "g1":
         cfg.gamma1_in[:] = list(value)
+    elif field == "flux":
+        cfg.diff_flux = value
+    elif field == "eta":
+        cfg.flux_eta = value
     elif field == "nan":
         cfg.coeffs.k = float("nan")
     elif field == "neg_diff":

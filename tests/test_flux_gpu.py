@@ -1,0 +1,102 @@
+"""GPU parity of the comparison diffusion fluxes (BR2, interior penalty,
+Baumann-Oden) against the oracle, through the C ABI."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.cdg2_oracle import Oracle, coeff_vector
+from parity_util import TOL, assert_close, make_case
+from paper_1403_1157_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def strong():
+    c = inputs.base_coeffs()
+    c.update(chi0_11=0.05, chi0_13=0.03, chi0_21=0.04, chi0_22=0.02)
+    return c
+
+
+def gpu_op(cfg, precision="fp64"):
+    from paper_1403_1157_amd.cdg2 import Operator
+    return Operator(cfg.dim, cfg.n, cfg.order, cfg.coeffs, precision=precision, wall_axis=cfg.wall_axis,
+                    llf_mode=cfg.llf_mode, gamma1_in=cfg.gamma1_in, diff_flux=cfg.diff_flux,
+                    flux_eta=cfg.flux_eta)
+
+
+CASES = [("br2", 3.0, 2, (5, 4), 2), ("ip", 5.0, 2, (5, 4), 2), ("bo", 0.0, 2, (5, 4), 2),
+         ("ip", 0.0, 2, (4, 5), 4), ("bo", 0.0, 2, (6, 3), 1), ("br2", 0.0, 3, (3, 3, 2), 2),
+         ("ip", 7.0, 3, (3, 2, 3), 1), ("bo", 0.0, 3, (2, 3, 3), 3)]
+
+
+@pytest.mark.parametrize("flux,eta,dim,n,p", CASES)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_flux_apply_parity(flux, eta, dim, n, p, precision):
+    U, cfg = make_case(dim, n, p, key=(10,), coeffs=strong())
+    cfg = dataclasses.replace(cfg, diff_flux=flux, flux_eta=eta)
+    Uin = U.float().double() if precision == "fp32" else U
+    ref = Oracle(cfg).apply(Uin)
+    op = gpu_op(cfg, precision)
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    out = op.apply(U.to(DEV, dt))
+    op.sync()
+    assert_close(out, ref, TOL[precision], f"{flux} d{dim} p{p} {precision}")
+
+
+@pytest.mark.parametrize("flux,eta", [("ip", 5.0), ("bo", 0.0)])
+def test_flux_rk_steps_parity(flux, eta):
+    U, cfg = make_case(2, (8, 6), 2, key=(11,), coeffs=strong())
+    cfg = dataclasses.replace(cfg, diff_flux=flux, flux_eta=eta)
+    o = Oracle(cfg)
+    op = gpu_op(cfg)
+    Ud = U.to(DEV)
+    dt = op.max_dt(Ud, 0.9)
+    ref = o.rk_step(U, dt, 6)
+    op.rk_step(Ud, dt, 6)
+    op.sync()
+    assert_close(Ud, ref, TOL["fp64"], f"{flux} rk")
+
+
+def test_ip_adjoint_parity_and_bo_adjoint_rejected():
+    from paper_1403_1157_amd.cdg2 import CDG2_EINVAL, CDG2Error
+    c = strong()
+    U, cfg = make_case(2, (6, 5), 2, key=(12,), coeffs=c)
+    cfg = dataclasses.replace(cfg, diff_flux="ip", flux_eta=5.0)
+    o = Oracle(cfg)
+    g = torch.Generator().manual_seed(2)
+    w = torch.randn(U.shape, generator=g, dtype=torch.float64)
+    th = coeff_vector(c).clone().requires_grad_(True)
+    X = U.clone().requires_grad_(True)
+    (o.apply(X, th) * w).sum().backward()
+    op = gpu_op(cfg)
+    out, dth = op.apply_adjoint(U.to(DEV), w.to(DEV), want_theta=True)
+    op.sync()
+    assert_close(out, X.grad, TOL["fp64"], "ip J^T w")
+    ref = th.grad[:21].numpy()
+    got = np.asarray(dth, dtype=np.float64)
+    scale = np.abs(ref).max()
+    rel = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * scale)
+    print(f"[ip adjoint] dtheta worst {rel.max():.3e} at {rel.argmax()}", flush=True)
+    assert rel.max() <= 1e-11
+    bo = gpu_op(dataclasses.replace(cfg, diff_flux="bo"))
+    with pytest.raises(CDG2Error) as ei:
+        bo.apply_adjoint(U.to(DEV), w.to(DEV))
+    assert ei.value.code == CDG2_EINVAL
+
+
+def test_br2_with_eta_n_equals_cdg2_and_cfl_constants():
+    U, cfg = make_case(3, (4, 3, 3), 2, key=(13,), coeffs=strong())
+    a = gpu_op(cfg)
+    b = gpu_op(dataclasses.replace(cfg, diff_flux="br2", flux_eta=6.0))
+    Ud = U.to(DEV)
+    fa, fb = a.apply(Ud), b.apply(Ud)
+    a.sync()
+    b.sync()
+    assert torch.equal(fa, fb)
+    assert a.rho_hat == b.rho_hat
+    ip = gpu_op(dataclasses.replace(cfg, diff_flux="ip", flux_eta=6.0))
+    bo = gpu_op(dataclasses.replace(cfg, diff_flux="bo"))
+    assert ip.rho_hat > a.rho_hat and bo.rho_hat > 0
