@@ -227,6 +227,39 @@ def bench_implicit(ratio=20.0, order=3):
             "implicit_over_explicit": round(ms_imp / ms_exp, 3), "max_abs_diff_vs_explicit": diff}
 
 
+def bench_fluxes(n=(128, 128), p=2, a=0.05, T=0.02):
+    """The comparison diffusion fluxes on the exact heat solution (the paper's
+    error-versus-time comparison, on this build's own problem): explicit dt of
+    each flux, GPU time to T and the L2 distance to the projected exact solution
+    (orthonormal modes: sqrt(|K| sum (U - P)^2), species n1)."""
+    import math
+
+    import torch
+
+    from paper_1403_1157_amd import inputs
+    from paper_1403_1157_amd.cdg2 import Operator
+
+    c = inputs.diffusion_only_coeffs(a)
+    U0 = torch.from_numpy(inputs.heat_modes(n, p, 0.0, a)).cuda()
+    P = torch.from_numpy(inputs.heat_modes(n, p, T, a)).cuda()
+    vol = 1.0 / (n[0] * n[1])
+    out = {}
+    for flux in ("cdg2", "br2", "ip", "bo"):
+        op = Operator(2, n, p, c, diff_flux=flux)
+        dt = op.max_dt(U0, 0.9)
+        nst = int(math.ceil(T / dt))
+        U = U0.clone()
+        op.rk_step(U, T / nst, 2)
+        op.sync()
+        U = U0.clone()
+        ms = time_ms(lambda: op.rk_step(U, T / nst, nst))
+        op.sync()
+        err = math.sqrt(vol * float(((U[0] - P[0]) ** 2).sum()))
+        out[flux] = {"dt": T / nst, "steps": nst, "ms": round(ms, 3), "l2_error_vs_projection": err}
+    return {"workload": f"heat solution, {n[0]}x{n[1]} Q{p}, a = {a}, T = {T}, SSP-RK3 at the CFL step",
+            "fluxes": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -327,6 +360,7 @@ def main():
         line["batched"] = bench_batched()
         line["adjoint"] = bench_adjoint()
         line["implicit"] = bench_implicit()
+        line["fluxes"] = bench_fluxes()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(dim, n, p, key, dof)
     print(json.dumps(line), flush=True)

@@ -170,3 +170,31 @@ def adjoint_target_coeffs(key: tuple = (4,)) -> dict:
     for name in COEFF_NAMES[:21]:
         c[name] = c[name] * (1.0 + 0.1 * (1.0 if rng.integers(0, 2) else -1.0))
     return c
+
+
+def diffusion_only_coeffs(a: float = 0.05) -> dict:
+    """Pure diffusion with the same motility a for every species: no chemotaxis,
+    no reactions, inflow switches off (thresholds above any field value)."""
+    c = {k: 0.0 for k in BASE}
+    for k in ("mu1", "mu2", "mu3", "nu1", "nu2", "nu3"):
+        c[k] = a
+    for k in ("chith_11", "chith_13", "chith_21", "chith_22"):
+        c[k] = 1.0
+    c["c1_star"] = 10.0
+    c["c1_sstar"] = 10.0
+    return c
+
+
+def heat_modes(n, p: int, t: float, a: float, amp: float = 0.2) -> np.ndarray:
+    """Projection onto Q_p of u = 0.5 + amp exp(-5 pi^2 a t) cos(2 pi x) cos(pi y)
+    (every species; solves u_t = a Laplace u, periodic in x, zero flux at y = 0, 1)
+    on an n[0] x n[1] grid: U[6, E, (p+1)^2]."""
+    nx, ny = int(n[0]), int(n[1])
+    q = p + 1
+    fx = _project_1d(lambda x: np.cos(2.0 * math.pi * x), nx, p)
+    fy = _project_1d(lambda y: np.cos(math.pi * y), ny, p)
+    term = np.einsum("ya,xb->yxab", fy, fx).reshape(nx * ny, q * q)
+    U = np.zeros((6, nx * ny, q * q))
+    U[:, :, 0] = 0.5
+    U += amp * math.exp(-5.0 * math.pi ** 2 * a * t) * term[None]
+    return U
