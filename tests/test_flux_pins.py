@@ -101,3 +101,20 @@ def test_comparison_fluxes_heat_equation_eoc(flux, eta, p, rho_mult):
         errs.append(o.l2_error(U, exact(T)))
     eoc = float(torch.log2(errs[0] / errs[1]).min())
     assert abs(eoc - (p + 1)) < 0.25, eoc
+
+
+def test_heat_solution_inputs_are_the_projection_of_the_exact_solution():
+    """The benchmark's heat-solution modes (numpy, inputs module) against the
+    oracle's L2 projection of the same function."""
+    a, t = 0.05, 0.013
+    n, p = (6, 5), 2
+    U = torch.from_numpy(inputs.heat_modes(n, p, t, a))
+    o = Oracle(Config(dim=2, n=n, order=p, coeffs=diffusion_only_coeffs(a)))
+
+    def f(x):
+        v = 0.5 + 0.2 * math.exp(-5 * math.pi ** 2 * a * t) * torch.cos(2 * math.pi * x[..., 0]) \
+            * torch.cos(math.pi * x[..., 1])
+        return torch.stack([v] * 6)
+
+    assert float((U - o.project(f)).abs().max()) < 1e-14
+    assert inputs.diffusion_only_coeffs(a) == diffusion_only_coeffs(a)
