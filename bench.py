@@ -76,10 +76,24 @@ def cpu_baseline(dim, n, p, key, dof):
     t = time.perf_counter()
     o.apply(U)
     sec = time.perf_counter() - t
+    # single-thread figure on a slab of the same grid (a quarter of the last axis)
+    n1 = tuple(n[:-1]) + (max(2, n[-1] // 4),)
+    U1 = torch.from_numpy(inputs.initial_modes(dim, n1, p, key))
+    o1 = Oracle(Config(dim=dim, n=n1, order=p, coeffs=inputs.base_coeffs()))
+    torch.set_num_threads(1)
+    try:
+        t = time.perf_counter()
+        o1.apply(U1)
+        sec1 = time.perf_counter() - t
+    finally:
+        torch.set_num_threads(threads)
     return {"value": round(dof / sec / 1e9, 6), "unit": "GDOF/s", "cores": threads,
             "kind": "oracle",
             "sample": f"one float64 oracle operator application on the full workload "
-                      f"({dof} DOF) in {sec:.2f} s; GDOF/s = DOF / seconds"}
+                      f"({dof} DOF) in {sec:.2f} s; GDOF/s = DOF / seconds",
+            "one_thread": {"value": round(U1.numel() / sec1 / 1e9, 6), "unit": "GDOF/s",
+                           "sample": f"one application on {'x'.join(map(str, n1))} cells "
+                                     f"({U1.numel()} DOF) in {sec1:.2f} s, 1 thread"}}
 
 
 def time_ms(fn, reps=1):
@@ -329,6 +343,32 @@ def main():
     ms_apply = ev0.elapsed_time(ev1) / args.steps
     op.sync()
 
+    # five more timed runs of the same K steps: median and minimum
+    trials = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            op.rk_step(U, dt, 1)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        trials.append(ev0.elapsed_time(ev1) / args.steps)
+    op.sync()
+    trials.sort()
+    # plain device copy of the state size: the bandwidth this machine reaches
+    src = U0.clone()
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(10):
+        dst.copy_(src)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 8 * 10 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del src, dst
+
     value = 3 * dof / (ms_step * 1e-3) / 1e9
     alg_bytes_step = 64.0 * dof
     achieved = alg_bytes_step / (ms_step * 1e-3) / 1e9
@@ -352,6 +392,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": traffic},
+        "trials_ms_per_step": {"median": round(trials[2], 5), "min": round(trials[0], 5),
+                               "max": round(trials[-1], 5)},
+        "copy_gb_s": round(copy_gbs, 1),
+        "frac_of_copy": round(achieved / copy_gbs, 4),
         "apply": {"us_per_apply": round(ms_apply * 1e3, 2),
                   "gdof_s": round(dof / (ms_apply * 1e-3) / 1e9, 4),
                   "alg_gb_s": round(16.0 * dof / (ms_apply * 1e-3) / 1e9, 2)},
