@@ -274,6 +274,48 @@ def bench_fluxes(n=(128, 128), p=2, a=0.05, T=0.02):
             "fluxes": out}
 
 
+def bench_2d(reps=1000, steps=100):
+    """The 256^2 workloads with Q2 and Q4: reps operator applications replayed
+    from one captured HIP graph, and a steps-long SSP-RK3 run."""
+    import torch
+
+    from paper_1403_1157_amd import inputs
+    from paper_1403_1157_amd.cdg2 import Operator
+
+    out = {}
+    for p in (2, 4):
+        n = (256, 256)
+        U0 = torch.from_numpy(inputs.initial_modes(2, n, p, (1,))).cuda()
+        dof = U0.numel()
+        op = Operator(2, n, p, inputs.base_coeffs())
+        dt = op.max_dt(U0, 0.9)
+        f = torch.empty_like(U0)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(3):
+                op.apply(U0, f)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(10):
+                op.apply(U0, f)
+        g.replay()
+        torch.cuda.synchronize()
+        ms_a = time_ms(lambda: [g.replay() for _ in range(reps // 10)]) / reps
+        U = U0.clone()
+        op.rk_step(U, dt, 2)
+        ms_s = time_ms(lambda: op.rk_step(U, dt, steps)) / steps
+        op.sync()
+        out[f"q{p}"] = {"us_per_apply_graph": round(ms_a * 1e3, 2),
+                        "apply_frac": round(16.0 * dof / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "us_per_step": round(ms_s * 1e3, 2),
+                        "step_frac": round(64.0 * dof / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "gdof_s": round(3 * dof / (ms_s * 1e-3) / 1e9, 3)}
+    return {"workload": f"256x256, {reps} graph-replayed applies and a {steps}-step SSP-RK3 run", **out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -401,6 +443,7 @@ def main():
                   "alg_gb_s": round(16.0 * dof / (ms_apply * 1e-3) / 1e9, 2)},
     }
     if not args.no_extras:
+        line["2d"] = bench_2d()
         line["batched"] = bench_batched()
         line["adjoint"] = bench_adjoint()
         line["implicit"] = bench_implicit()
