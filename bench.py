@@ -243,7 +243,7 @@ def bench_implicit(ratio=20.0, order=3):
 
 def bench_fluxes(n=(128, 128), p=2, a=0.05, T=0.02):
     """The comparison diffusion fluxes on the exact heat solution (the paper's
-    error-versus-time comparison, on this build's own problem): explicit dt of
+    error-versus-time comparison, on a problem with a known solution): explicit dt of
     each flux, GPU time to T and the L2 distance to the projected exact solution
     (orthonormal modes: sqrt(|K| sum (U - P)^2), species n1)."""
     import math
@@ -324,14 +324,14 @@ def main():
     ap.add_argument("--workload", default="3d-q2-64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched, adjoint and implicit measurements")
+                    help="skip the 2D, batched, adjoint, implicit and flux measurements")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM "
                          "byte counters of a profiler run) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              "slab decomposition is a design, not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the slab "
+              "decomposition over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch

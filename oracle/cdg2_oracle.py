@@ -26,7 +26,7 @@ matrix is likewise assembled and solved, not assumed diagonal.  All arithmetic i
 torch float64 on the CPU and differentiable, so torch.autograd gives the exact
 discrete adjoint (vector-Jacobian products) of every function here.
 
-Readings where the paper is silent or garbled (each one is listed in the design doc):
+Readings where the paper is silent or garbled:
   * grid: uniform Cartesian cells on [0,1]^d, tensor Legendre Q_p basis
     phi_i(xi) = sqrt(2i+1) P_i(2 xi - 1) per direction (orthonormal on [0,1]);
   * p+1 Gauss-Legendre points per direction for volume and face integrals;
