@@ -12,7 +12,14 @@ float64), inputs resident in HBM.  Prints ONE JSON line.
   cpu_baseline the float64 oracle (test infrastructure) timed on the host cores
                for one operator application of the same workload
 
+Extras in the same line (skipped with --no-extras): the 256^2 Q2/Q4 workloads
+(graph-replayed applies, 100-step runs), the batched 256-instance run against
+the plain entry point, the adjoint (forward + gradient against forward), the
+implicit SDIRK step against the explicit steps over the same interval, and the
+comparison diffusion fluxes on the exact heat solution.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+(default K = 50: the 50-step run of the 64^3 workload)
 """
 import argparse
 import hashlib
@@ -319,7 +326,7 @@ def bench_2d(reps=1000, steps=100):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="3d-q2-64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
