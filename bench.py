@@ -136,7 +136,7 @@ def bench_batched(steps=50):
     dof = sum(U.numel() for U in states)
     bt = Batch(insts)
     packed = bt.pack(states)
-    tune = bt.autotune(packed, dts)
+    tune = bt.autotune()
     work = packed.clone()
     bt.rk(work, dts, steps)          # capture + warm the graph
     bt.sync()

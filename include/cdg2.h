@@ -242,7 +242,7 @@ typedef struct cdg2_batch cdg2_batch;
 
 /* Copy count configs (2D, FP64, order <= 3; else CDG2_EINVAL), allocate the
  * descriptor table, work list and two packed stage buffers (CDG2_ENOMEM). */
-int cdg2_batch_create(const cdg2_config* cfgs, int count, cdg2_batch** out);
+int cdg2_batch_create(const cdg2_config* cfgs, int count, int autotune, cdg2_batch** out);
 int cdg2_batch_destroy(cdg2_batch* b);
 int cdg2_batch_set_stream(cdg2_batch* b, void* hip_stream);
 /* Total entries of the packed state, and the element offset of instance i
@@ -253,11 +253,23 @@ size_t cdg2_batch_offset(const cdg2_batch* b, int i);
  * workgroup), nwg = persistent workgroups (0: one per item), order = 0 items
  * sorted by decreasing cost, 1 in instance order.  Rebuilds the work list. */
 int cdg2_batch_set_schedule(cdg2_batch* b, int eb, int nwg, int order);
+/* Autotuner: times one SSP-RK3 step of every candidate schedule (eb in
+ * {16, 32, 64}, nwg in {0, 1, 2, 4} x the number of compute units, both item
+ * orders) on a zero scratch state with dt = 0 (the kernels do their full work)
+ * and keeps the fastest; writes eb, nwg, order and its time in ms into
+ * best[0..3] if best is not NULL.  Allocates and frees the scratch state; waits
+ * for the device.  cdg2_batch_create with autotune != 0 calls it. */
+int cdg2_batch_autotune(cdg2_batch* b, double* best);
+/* Run the stages as one captured HIP graph per (U_packed, offsets, nsteps)
+ * (on != 0, the default) or launch them one by one (on = 0). */
+int cdg2_batch_set_graph(cdg2_batch* b, int on);
 /* nsteps SSP-RK3 steps of every instance, in place on the packed device buffer
  * U_packed, instance i with time step dts[i] (HOST array of count doubles).
- * use_graph != 0: the 3*nsteps launches are captured once per (U_packed,
- * nsteps) into a HIP graph and replayed.  Asynchronous; see cdg2_batch_sync. */
-int cdg2_batch_rk(cdg2_batch* b, void* U_packed, const double* dts, int nsteps, int use_graph);
+ * offsets: NULL for the library's packing (cdg2_batch_offset), else a HOST
+ * array of count element offsets placing the instances anywhere inside the
+ * first cdg2_batch_num_dofs entries of U_packed without overlap (CDG2_EINVAL
+ * otherwise).  Asynchronous; see cdg2_batch_sync. */
+int cdg2_batch_rk(cdg2_batch* b, void* U_packed, const size_t* offsets, const double* dts, int nsteps);
 /* Wait for the batch's stream; report non-finite / domain conditions. */
 int cdg2_batch_sync(cdg2_batch* b);
 

@@ -91,7 +91,9 @@ def lib():
     L.cdg2_rk_adjoint_segment.argtypes = [P, P, ctypes.c_int, _d, P, ctypes.POINTER(_d)]
     L.cdg2_dirk_step.argtypes = [P, P, _d, ctypes.POINTER(cdg2_implicit_opts),
                                  ctypes.POINTER(cdg2_implicit_stats)]
-    L.cdg2_batch_create.argtypes = [ctypes.POINTER(cdg2_config), ctypes.c_int, ctypes.POINTER(P)]
+    L.cdg2_batch_create.argtypes = [ctypes.POINTER(cdg2_config), ctypes.c_int, ctypes.c_int, ctypes.POINTER(P)]
+    L.cdg2_batch_autotune.argtypes = [P, ctypes.POINTER(_d)]
+    L.cdg2_batch_set_graph.argtypes = [P, ctypes.c_int]
     L.cdg2_batch_destroy.argtypes = [P]
     L.cdg2_batch_set_stream.argtypes = [P, P]
     L.cdg2_batch_num_dofs.argtypes = [P]
@@ -99,7 +101,7 @@ def lib():
     L.cdg2_batch_offset.argtypes = [P, ctypes.c_int]
     L.cdg2_batch_offset.restype = ctypes.c_size_t
     L.cdg2_batch_set_schedule.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
-    L.cdg2_batch_rk.argtypes = [P, P, ctypes.POINTER(_d), ctypes.c_int, ctypes.c_int]
+    L.cdg2_batch_rk.argtypes = [P, P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_d), ctypes.c_int]
     L.cdg2_batch_sync.argtypes = [P]
     L.cdg2_last_error.argtypes = []
     L.cdg2_last_error.restype = ctypes.c_char_p
@@ -109,7 +111,7 @@ def lib():
                  "cdg2_dirk_step",
                  "cdg2_batch_create",
                  "cdg2_batch_destroy", "cdg2_batch_set_stream", "cdg2_batch_set_schedule",
-                 "cdg2_batch_rk", "cdg2_batch_sync"):
+                 "cdg2_batch_rk", "cdg2_batch_sync", "cdg2_batch_autotune", "cdg2_batch_set_graph"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -230,11 +232,22 @@ def cdg2_dirk_step(h, U_ptr: int, dt: float, opts: cdg2_implicit_opts | None = N
     return stats
 
 
-def cdg2_batch_create(cfgs) -> ctypes.c_void_p:
+def cdg2_batch_create(cfgs, autotune: bool = False) -> ctypes.c_void_p:
     arr = (cdg2_config * len(cfgs))(*cfgs)
     h = ctypes.c_void_p()
-    _check(lib().cdg2_batch_create(arr, len(cfgs), ctypes.byref(h)))
+    _check(lib().cdg2_batch_create(arr, len(cfgs), 1 if autotune else 0, ctypes.byref(h)))
     return h
+
+
+def cdg2_batch_autotune(b) -> tuple:
+    """Native autotuner: returns ((eb, nwg, order), ms per step) of the chosen schedule."""
+    best = (_d * 4)()
+    _check(lib().cdg2_batch_autotune(b, best))
+    return (int(best[0]), int(best[1]), int(best[2])), float(best[3])
+
+
+def cdg2_batch_set_graph(b, on: bool) -> None:
+    _check(lib().cdg2_batch_set_graph(b, 1 if on else 0))
 
 
 def cdg2_batch_destroy(b) -> None:
@@ -257,9 +270,11 @@ def cdg2_batch_set_schedule(b, eb: int, nwg: int, order: int) -> None:
     _check(lib().cdg2_batch_set_schedule(b, int(eb), int(nwg), int(order)))
 
 
-def cdg2_batch_rk(b, U_ptr: int, dts, nsteps: int, use_graph: bool = True) -> None:
+def cdg2_batch_rk(b, U_ptr: int, offsets, dts, nsteps: int) -> None:
+    """offsets: None (the library's packing) or a sequence of element offsets."""
     arr = (_d * len(dts))(*[float(x) for x in dts])
-    _check(lib().cdg2_batch_rk(b, ctypes.c_void_p(U_ptr), arr, int(nsteps), 1 if use_graph else 0))
+    offs = None if offsets is None else (ctypes.c_size_t * len(offsets))(*[int(x) for x in offsets])
+    _check(lib().cdg2_batch_rk(b, ctypes.c_void_p(U_ptr), offs, arr, int(nsteps)))
 
 
 def cdg2_batch_sync(b) -> None:

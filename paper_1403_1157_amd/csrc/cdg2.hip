@@ -854,6 +854,8 @@ struct cdg2_batch {
   hipGraphExec_t gexec = nullptr;
   void* g_U = nullptr;
   int g_nsteps = -1;
+  int use_graph = 1;
+  std::vector<size_t> packing;   // the library's offsets
 };
 
 namespace {
@@ -917,7 +919,7 @@ hipError_t batch_launch(cdg2_batch* b, hipStream_t st, double* U, int stage) {
 
 extern "C" {
 
-int cdg2_batch_create(const cdg2_config* cfgs, int count, cdg2_batch** out) {
+int cdg2_batch_create(const cdg2_config* cfgs, int count, int autotune, cdg2_batch** out) {
   if (!out || !cfgs || count <= 0) return fail(CDG2_EINVAL, "bad arguments");
   *out = nullptr;
   for (int i = 0; i < count; ++i) {
@@ -940,6 +942,7 @@ int cdg2_batch_create(const cdg2_config* cfgs, int count, cdg2_batch** out) {
     coef_from(cfgs[i].coeffs, &in.prm.cf);
     in.p = cfgs[i].order;
     in.off = off;
+    b->packing.push_back(off);
     const size_t nd = 6 * (size_t)in.prm.g.E * (size_t)((in.p + 1) * (in.p + 1));
     b->ndof[i] = nd;
     off += nd;
@@ -959,11 +962,90 @@ int cdg2_batch_create(const cdg2_config* cfgs, int count, cdg2_batch** out) {
     return fail(CDG2_EHIP, "batch initialisation failed");
   }
   int rc = batch_build_items(b);
+  if (!rc && autotune) rc = cdg2_batch_autotune(b, nullptr);
   if (rc) {
     cdg2_batch_destroy(b);
     return rc;
   }
   *out = b;
+  return CDG2_OK;
+}
+
+int cdg2_batch_autotune(cdg2_batch* b, double* best) {
+  if (!b) return fail(CDG2_EINVAL, "batch is NULL");
+  int dev = 0, ncu = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  double* W = nullptr;
+  if (hipMalloc((void**)&W, b->total * sizeof(double)) != hipSuccess)
+    return fail(CDG2_ENOMEM, "hipMalloc of the autotuning state failed");
+  std::vector<BatchInst> saved = b->insts;
+  for (auto& in : b->insts) {
+    in.dt = 0.0;
+    in.off = b->packing[&in - b->insts.data()];
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMemsetAsync(W, 0, b->total * sizeof(double), b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_insts, b->insts.data(), b->count * sizeof(BatchInst), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  const int ebs[3] = {16, 32, 64}, wpc[4] = {0, 1, 2, 4};
+  double tbest = 1e300;
+  int bb[3] = {32, 0, 0};
+  for (int ie = 0; ie < 3 && e == hipSuccess; ++ie)
+    for (int iw = 0; iw < 4 && e == hipSuccess; ++iw)
+      for (int order = 0; order < 2 && e == hipSuccess; ++order) {
+        b->eb = ebs[ie];
+        b->nwg = wpc[iw] * ncu;
+        b->order = order;
+        int rc = batch_build_items(b);
+        if (rc) {
+          e = hipErrorUnknown;
+          break;
+        }
+        for (int st = 1; st <= 3 && e == hipSuccess; ++st) e = batch_launch(b, b->stream, W, st);   // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep)
+          for (int st = 1; st <= 3 && e == hipSuccess; ++st) e = batch_launch(b, b->stream, W, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && ms / 3.0 < tbest) {
+          tbest = ms / 3.0;
+          bb[0] = b->eb;
+          bb[1] = b->nwg;
+          bb[2] = b->order;
+        }
+      }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(b->stream);
+  (void)hipFree(W);
+  // restore the caller's time steps and placement, clear what the zero state raised
+  b->insts = saved;
+  hipError_t e2 = hipMemcpy(b->d_insts, b->insts.data(), b->count * sizeof(BatchInst), hipMemcpyHostToDevice);
+  if (e2 == hipSuccess) e2 = hipMemset(b->flags, 0, sizeof(int));
+  if (e != hipSuccess || e2 != hipSuccess)
+    return fail(CDG2_EHIP, "autotuning failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  b->eb = bb[0];
+  b->nwg = bb[1];
+  b->order = bb[2];
+  int rc = batch_build_items(b);
+  if (rc) return rc;
+  if (best) {
+    best[0] = bb[0];
+    best[1] = bb[1];
+    best[2] = bb[2];
+    best[3] = tbest;
+  }
+  return CDG2_OK;
+}
+
+int cdg2_batch_set_graph(cdg2_batch* b, int on) {
+  if (!b) return fail(CDG2_EINVAL, "batch is NULL");
+  b->use_graph = on != 0;
   return CDG2_OK;
 }
 
@@ -1003,22 +1085,38 @@ int cdg2_batch_set_schedule(cdg2_batch* b, int eb, int nwg, int order) {
   return batch_build_items(b);
 }
 
-int cdg2_batch_rk(cdg2_batch* b, void* U_packed, const double* dts, int nsteps, int use_graph) {
+int cdg2_batch_rk(cdg2_batch* b, void* U_packed, const size_t* offsets, const double* dts, int nsteps) {
   if (!b || !U_packed || !dts) return fail(CDG2_EINVAL, "NULL argument");
   if (nsteps < 0) return fail(CDG2_EINVAL, "nsteps < 0");
   if (overlap(U_packed, b->S0, b->total * 8) || overlap(U_packed, b->S1, b->total * 8))
     return fail(CDG2_EINVAL, "U_packed overlaps a stage buffer");
+  const size_t* off = offsets ? offsets : b->packing.data();
+  if (offsets) {
+    // any non-overlapping placement inside the packed size (the stage buffers
+    // use the same offsets)
+    std::vector<int> idx(b->count);
+    for (int i = 0; i < b->count; ++i) {
+      idx[i] = i;
+      if (off[i] > b->total || b->ndof[i] > b->total - off[i])
+        return fail(CDG2_EINVAL, "offset of instance %d leaves the packed size", i);
+    }
+    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return off[x] < off[y]; });
+    for (int k = 1; k < b->count; ++k)
+      if (off[idx[k - 1]] + b->ndof[idx[k - 1]] > off[idx[k]])
+        return fail(CDG2_EINVAL, "instances %d and %d overlap", idx[k - 1], idx[k]);
+  }
   bool changed = false;
   for (int i = 0; i < b->count; ++i) {
     if (!std::isfinite(dts[i])) return fail(CDG2_EINVAL, "dt of instance %d is not finite", i);
-    if (b->insts[i].dt != dts[i]) changed = true;
+    if (b->insts[i].dt != dts[i] || b->insts[i].off != off[i]) changed = true;
     b->insts[i].dt = dts[i];
+    b->insts[i].off = off[i];
   }
   if (changed)
     HIP_TRY(hipMemcpyAsync(b->d_insts, b->insts.data(), b->count * sizeof(BatchInst), hipMemcpyHostToDevice,
                            b->stream));
   double* U = (double*)U_packed;
-  if (!use_graph || nsteps == 0) {
+  if (!b->use_graph || nsteps == 0) {
     for (int n = 0; n < nsteps; ++n)
       for (int st = 1; st <= 3; ++st) HIP_TRY(batch_launch(b, b->stream, U, st));
     return CDG2_OK;

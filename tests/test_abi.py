@@ -98,5 +98,9 @@ def test_null_arguments_rejected():
     assert L.cdg2_rk_step_adjoint(None, None, None, None, 0.1, None) == B.CDG2_EINVAL
     assert L.cdg2_rk_adjoint_segment(None, None, 1, 0.1, None, None) == B.CDG2_EINVAL
     assert L.cdg2_dirk_step(None, None, 0.1, None, None) == B.CDG2_EINVAL
+    assert L.cdg2_batch_autotune(None, None) == B.CDG2_EINVAL
+    assert L.cdg2_batch_set_graph(None, 1) == B.CDG2_EINVAL
+    assert L.cdg2_batch_rk(None, None, None, None, 1) == B.CDG2_EINVAL
+    assert L.cdg2_batch_create(None, 0, 0, None) == B.CDG2_EINVAL
     assert L.cdg2_destroy(None) == B.CDG2_OK
     assert L.cdg2_num_dofs(None) == 0

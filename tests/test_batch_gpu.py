@@ -68,6 +68,58 @@ def test_batched_equals_per_instance(schedule, graph):
     bt.close()
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_caller_offsets_place_instances_anywhere(graph):
+    """cdg2_batch_rk with caller offsets (the instances in reverse order inside the
+    same packed size) gives the same per-instance results as the library's
+    packing; an overlapping or out-of-range placement is rejected."""
+    from paper_1403_1157_amd.batch import Batch
+    from paper_1403_1157_amd.cdg2 import CDG2_EINVAL, CDG2Error
+    insts = small_batch(7, seed=4)
+    states = states_for(insts)
+    dts = dts_for(insts, states)
+    ref = per_instance(insts, states, dts, 2)
+    bt = Batch(insts)
+    sizes = [s[0] * s[1] * s[2] for s in bt.shapes]
+    offs, pos = [0] * len(insts), 0
+    for i in reversed(range(len(insts))):
+        offs[i] = pos
+        pos += sizes[i]
+    packed = torch.empty(bt.total, dtype=torch.float64, device=DEV)
+    for i, U in enumerate(states):
+        packed[offs[i]:offs[i] + sizes[i]] = U.reshape(-1)
+    bt.rk(packed, dts, 2, graph=graph, offsets=offs)
+    bt.sync()
+    for i in range(len(insts)):
+        assert torch.equal(packed[offs[i]:offs[i] + sizes[i]].view(bt.shapes[i]), ref[i]), i
+    bad = list(offs)
+    bad[0] = offs[1]                       # overlaps instance 1
+    with pytest.raises(CDG2Error) as ei:
+        bt.rk(packed, dts, 1, offsets=bad)
+    assert ei.value.code == CDG2_EINVAL
+    bad = list(offs)
+    bad[2] = bt.total - sizes[2] + 1       # leaves the packed size
+    with pytest.raises(CDG2Error) as ei:
+        bt.rk(packed, dts, 1, offsets=bad)
+    assert ei.value.code == CDG2_EINVAL
+    bt.close()
+
+
+def test_create_with_native_autotune():
+    from paper_1403_1157_amd.batch import Batch
+    insts = small_batch(6, seed=2)
+    states = states_for(insts)
+    dts = dts_for(insts, states)
+    ref = per_instance(insts, states, dts, 2)
+    bt = Batch(insts, autotune=True)
+    packed = bt.pack(states)
+    bt.rk(packed, dts, 2)
+    bt.sync()
+    for i in range(len(insts)):
+        assert torch.equal(bt.view(packed, i), ref[i]), i
+    bt.close()
+
+
 def test_graph_replays_match_eager():
     """Replay the captured graph several times with eager work and
     synchronisations between replays; every replay equals the eager run."""
@@ -116,7 +168,7 @@ def test_full_batch_sample_and_autotuner(tmp_path):
     dts = dts_for(insts, states)
     bt = Batch(insts)
     packed = bt.pack(states)
-    best = bt.autotune(packed, dts, cache_path=str(tmp_path / "tune.json"))
+    best = bt.autotune(cache_path=str(tmp_path / "tune.json"))
     print(f"[batch] autotuned schedule {best['schedule']} {best['ms_per_step']:.3f} ms/step", flush=True)
     assert (tmp_path / "tune.json").exists()
     bt.rk(packed, dts, 2)
