@@ -25,7 +25,9 @@
  * float32 (CDG2_FP32).
  *
  * Ownership: every state pointer is a DEVICE pointer to a caller-owned,
- * contiguous buffer on the handle's device.  The library owns its tables, two
+ * contiguous buffer on the handle's device; in 3D the buffers passed to the
+ * operator and RK entry points must be 16-byte aligned (CDG2_EINVAL otherwise;
+ * device allocations are).  The library owns its tables, two
  * stage buffers and small flag buffers; it copies the config at create.
  *
  * Asynchrony: calls that take device pointers enqueue work on the stream set by

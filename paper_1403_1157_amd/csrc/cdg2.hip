@@ -275,6 +275,12 @@ bool overlap(const void* a, const void* b, size_t bytes) {
   return x < y + bytes && y < x + bytes;
 }
 
+// 3D launches move whole cells with 16-byte load-to-LDS chunks: their state
+// buffers must be 16-byte aligned (device allocations are)
+bool misaligned(const cdg2_handle* h, const void* p) {
+  return h->dim == 3 && ((uintptr_t)p & 15) != 0;
+}
+
 // [a, a + na) and [b, b + nb) intersect
 bool overlap2(const void* a, size_t na, const void* b, size_t nb) {
   const char* x = (const char*)a;
@@ -519,6 +525,7 @@ int cdg2_apply_operator(cdg2_handle* h, const void* U, void* dUdt) {
   if (!h || !U || !dUdt) return fail(CDG2_EINVAL, "NULL argument");
   size_t bytes = h->ndof * (h->fp32 ? 4 : 8);
   if (overlap(U, dUdt, bytes)) return fail(CDG2_EINVAL, "U and dUdt overlap");
+  if (misaligned(h, U) || misaligned(h, dUdt)) return fail(CDG2_EINVAL, "3D state buffers must be 16-byte aligned");
   HIP_TRY(run_op(h, U, nullptr, dUdt, 0.0, 0.0, 1.0, 0));
   return CDG2_OK;
 }
@@ -530,6 +537,7 @@ int cdg2_rk_step(cdg2_handle* h, void* U, double dt, int nsteps) {
   size_t bytes = h->ndof * (h->fp32 ? 4 : 8);
   if (overlap(U, h->stage[0], bytes) || overlap(U, h->stage[1], bytes))
     return fail(CDG2_EINVAL, "U overlaps a stage buffer");
+  if (misaligned(h, U)) return fail(CDG2_EINVAL, "3D state buffers must be 16-byte aligned");
   for (int n = 0; n < nsteps; ++n) {
     HIP_TRY(run_op(h, U, nullptr, h->stage[0], dt, 0.0, 1.0, 1));
     HIP_TRY(run_op(h, h->stage[0], U, h->stage[1], dt, 0.75, 0.25, 2));
@@ -559,6 +567,7 @@ int cdg2_rk_step_adjoint(cdg2_handle* h, const void* U_n, const void* lam_np1, v
   if (!std::isfinite(dt)) return fail(CDG2_EINVAL, "dt is not finite");
   size_t bytes = h->ndof * (h->fp32 ? 4 : 8);
   if (overlap(lam_n, U_n, bytes)) return fail(CDG2_EINVAL, "lam_n overlaps U_n");
+  if (misaligned(h, U_n)) return fail(CDG2_EINVAL, "3D state buffers must be 16-byte aligned");
   int rc = ensure_adjoint(h);
   if (rc) return rc;
   const int th = dtheta_acc != nullptr;

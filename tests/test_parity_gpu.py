@@ -164,3 +164,26 @@ def test_apply_is_deterministic():
     b = op.apply(Ud)
     op.sync()
     assert torch.equal(a, b)
+
+
+def test_3d_state_buffers_must_be_16_byte_aligned():
+    """3D launches load whole cells in 16-byte chunks: an 8-byte-aligned view is
+    rejected before any launch, an aligned one runs."""
+    from paper_1403_1157_amd.cdg2 import CDG2_EINVAL, CDG2Error
+    U, cfg = make_case(3, (3, 2, 2), 1, key=(1,))
+    op = gpu_op(cfg)
+    n = U.numel()
+    buf = torch.zeros(n + 2, dtype=torch.float64, device=DEV)
+    bad = buf[1:1 + n].view(U.shape)
+    bad.copy_(U.to(DEV))
+    with pytest.raises(CDG2Error) as ei:
+        op.apply(bad)
+    assert ei.value.code == CDG2_EINVAL
+    with pytest.raises(CDG2Error) as ei:
+        op.rk_step(bad, 1e-4, 1)
+    assert ei.value.code == CDG2_EINVAL
+    good = buf[2:2 + n].view(U.shape)
+    good.copy_(U.to(DEV))
+    out = op.apply(good)
+    op.sync()
+    assert torch.isfinite(out).all()
