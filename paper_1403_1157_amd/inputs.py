@@ -198,3 +198,38 @@ def heat_modes(n, p: int, t: float, a: float, amp: float = 0.2) -> np.ndarray:
     U[:, :, 0] = 0.5
     U += amp * math.exp(-5.0 * math.pi ** 2 * a * t) * term[None]
     return U
+
+
+def reduced_3d_coeffs(base: dict | None = None) -> dict:
+    """The three-species model of the paper's 3D experiment (immune cells n1,
+    debris n3, chemoattractant c1, eq. (02)) as a coefficient set of the
+    six-species model: run with n2 = c2 = c3 = 0 (they stay zero: no sources,
+    no inflow of LDL (sigma = 0) or of smooth muscle cells (beta2 = 0)), n1
+    without its death term and the debris source (d1 - F) n1 kept, i.e.
+    d1 := 0 and gamma := gamma - d1.  The immune-cell inflow on Gamma1 stays."""
+    c = dict(base_coeffs() if base is None else base)
+    c["gamma"] = c["gamma"] - c["d1"]
+    c["d1"] = 0.0
+    c["sigma"] = 0.0
+    c["beta2"] = 0.0
+    return c
+
+
+def reduced_3d_modes(n, p: int, key: tuple = (6,)) -> np.ndarray:
+    """Initial data of the 3D experiment: the seeded n1 and c1 fields, a local
+    bump of debris n3 (the inflammation trigger: no LDL inflow in 3D), and
+    n2 = c2 = c3 = 0.  The bump is exp(-|x - x0|^2 / (2 s^2)) projected per axis
+    (separable), amplitude 0.5, s = 0.08, x0 = (0.5, 0.5, 0.15)."""
+    U = initial_modes(3, n, p, key)
+    U[1] = 0.0                                  # n2
+    U[4] = 0.0                                  # c2
+    U[5] = 0.0                                  # c3
+    q = p + 1
+    facs = []
+    for b, x0 in enumerate((0.5, 0.5, 0.15)):
+        facs.append(_project_1d(lambda x, x0=x0: np.exp(-((x - x0) ** 2) / (2 * 0.08 ** 2)), int(n[b]), p))
+    bump = np.einsum("zc,yb,xa->zyxcba", facs[2], facs[1], facs[0]).reshape(-1, q ** 3)
+    U[2] = 0.0
+    U[2, :, 0] = 0.05
+    U[2] += 0.5 * bump
+    return U
