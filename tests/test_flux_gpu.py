@@ -100,3 +100,28 @@ def test_br2_with_eta_n_equals_cdg2_and_cfl_constants():
     ip = gpu_op(dataclasses.replace(cfg, diff_flux="ip", flux_eta=6.0))
     bo = gpu_op(dataclasses.replace(cfg, diff_flux="bo"))
     assert ip.rho_hat > a.rho_hat and bo.rho_hat > 0
+
+
+def test_br2_rk_step_adjoint_parity():
+    """The RK-step adjoint with a comparison flux (BR2, eta = 3) against the
+    oracle's vector-Jacobian product of the same step."""
+    c = strong()
+    U, cfg = make_case(2, (6, 5), 2, key=(14,), coeffs=c)
+    cfg = dataclasses.replace(cfg, diff_flux="br2", flux_eta=3.0)
+    o = Oracle(cfg)
+    op = gpu_op(cfg)
+    dt = op.max_dt(U.to(DEV), 0.9)
+    g = torch.Generator().manual_seed(5)
+    lam = torch.randn(U.shape, generator=g, dtype=torch.float64)
+    th = coeff_vector(c).clone().requires_grad_(True)
+    X = U.clone().requires_grad_(True)
+    (o.rk_step(X, dt, 1, theta=th) * lam).sum().backward()
+    lam_d = lam.to(DEV)
+    dth = torch.zeros(21, dtype=torch.float64, device=DEV)
+    op.rk_step_adjoint(U.to(DEV), lam_d, lam_d, dt, dth)
+    op.sync()
+    assert_close(lam_d, X.grad, TOL["fp64"], "br2 RK adjoint")
+    ref = th.grad[:21].numpy()
+    got = dth.cpu().numpy()
+    rel = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+    assert rel.max() <= 1e-11, rel.max()
