@@ -37,7 +37,7 @@ def theta_close(g, o, tol):
 
 
 ADJ_CASES = [(2, (6, 5), 1, "all"), (2, (8, 7), 2, "all"), (2, (5, 6), 3, "cells"), (2, (4, 5), 4, "all"),
-             (3, (4, 3, 4), 1, "all"), (3, (4, 4, 3), 2, "all")]
+             (3, (4, 3, 4), 1, "all"), (3, (4, 4, 3), 2, "all"), (3, (3, 3, 2), 3, "cells")]
 
 
 @pytest.mark.parametrize("dim,n,p,mode", ADJ_CASES)
