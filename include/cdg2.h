@@ -253,11 +253,12 @@ size_t cdg2_batch_num_dofs(const cdg2_batch* b);
 size_t cdg2_batch_offset(const cdg2_batch* b, int i);
 /* Schedule: eb = cells per work item (16, 32 or 64; 6*eb threads per
  * workgroup), nwg = persistent workgroups (0: one per item), order = 0 items
- * sorted by decreasing cost, 1 in instance order.  Rebuilds the work list. */
+ * sorted by decreasing cost, 1 in instance order, 2 one launch per polynomial
+ * order (each with its own occupancy; nwg per launch).  Rebuilds the work list. */
 int cdg2_batch_set_schedule(cdg2_batch* b, int eb, int nwg, int order);
 /* Autotuner: times one SSP-RK3 step of every candidate schedule (eb in
- * {16, 32, 64}, nwg in {0, 1, 2, 4} x the number of compute units, both item
- * orders) on a zero scratch state with dt = 0 (the kernels do their full work)
+ * {16, 32, 64}, nwg in {0, 1, 2, 4} x the number of compute units, order 0, 1
+ * and 2) on a zero scratch state with dt = 0 (the kernels do their full work)
  * and keeps the fastest; writes eb, nwg, order and its time in ms into
  * best[0..3] if best is not NULL.  Allocates and frees the scratch state; waits
  * for the device.  cdg2_batch_create with autotune != 0 calls it. */

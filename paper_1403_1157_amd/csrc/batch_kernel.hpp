@@ -77,6 +77,34 @@ batch_stage_kernel(const BatchInst* __restrict__ insts, const WorkItem* __restri
   }
 }
 
+// The same stage for work items of one order P only (one launch per order):
+// each launch gets the occupancy of its own order's registers and LDS.
+template <typename T, int EB, int P>
+__global__ void __launch_bounds__(6 * EB)
+batch_stage_kernel_p(const BatchInst* __restrict__ insts, const WorkItem* __restrict__ items, int nitems,
+                     T* U, T* S0, T* S1, int stage, int* __restrict__ flags) {
+  __shared__ EsSmem<2, P, T, EB> sm;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const WorkItem wi = items[it];
+    const BatchInst& in = insts[wi.inst];
+    const size_t off = in.off;
+    const T dt = T(in.dt);
+    const T* src;
+    const T* u0;
+    T* dst;
+    T ca, cb;
+    if (stage == 1) {
+      src = U + off; u0 = nullptr; dst = S0 + off; ca = T(0); cb = T(1);
+    } else if (stage == 2) {
+      src = S0 + off; u0 = U + off; dst = S1 + off; ca = T(0.75); cb = T(0.25);
+    } else {
+      src = S1 + off; u0 = U + off; dst = U + off; ca = T(1.0 / 3.0); cb = T(2.0 / 3.0);
+    }
+    es_block<2, P, T, EB>(in.prm, src, u0, dst, dt, ca, cb, stage, flags, wi.e0, sm);
+    __syncthreads();   // the next item reuses the LDS buffer
+  }
+}
+
 // Fill a buffer with a constant (autotuning inputs).
 template <typename T>
 __global__ void fill_kernel(T* x, size_t n, T v) {

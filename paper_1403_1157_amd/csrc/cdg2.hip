@@ -859,6 +859,7 @@ struct cdg2_batch {
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;
   int eb = 32, nwg = 0, order = 0;
+  int pstart[4] = {0, 0, 0, 0}, pcount[4] = {0, 0, 0, 0};   // order 2: item range per p
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   void* g_U = nullptr;
@@ -889,13 +890,22 @@ int batch_build_items(cdg2_batch* b) {
       cost.push_back((double)q * q * q);
     }
   }
-  if (b->order == 0) {
+  if (b->order == 0 || b->order == 2) {
     std::vector<int> idx(items.size());
     for (size_t k = 0; k < idx.size(); ++k) idx[k] = (int)k;
     std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return cost[x] > cost[y]; });
     std::vector<WorkItem> sorted(items.size());
     for (size_t k = 0; k < idx.size(); ++k) sorted[k] = items[idx[k]];
     items.swap(sorted);
+  }
+  for (int p = 0; p < 4; ++p) b->pstart[p] = b->pcount[p] = 0;
+  if (b->order == 2) {
+    // cost-sorted is order-sorted (cost = (p+1)^3): record each order's range
+    for (size_t k = 0; k < items.size(); ++k) {
+      const int p = b->insts[items[k].inst].p;
+      if (b->pcount[p] == 0) b->pstart[p] = (int)k;
+      ++b->pcount[p];
+    }
   }
   if (b->d_items) (void)hipFree(b->d_items);
   b->d_items = nullptr;
@@ -916,7 +926,32 @@ hipError_t batch_launch_eb(cdg2_batch* b, hipStream_t st, double* U, int stage) 
   return hipGetLastError();
 }
 
+template <int EB, int P>
+hipError_t batch_launch_p(cdg2_batch* b, hipStream_t st, double* U, int stage) {
+  const int cnt = b->pcount[P];
+  if (cnt == 0) return hipSuccess;
+  int grid = b->nwg > 0 ? std::min(b->nwg, cnt) : cnt;
+  hipLaunchKernelGGL((batch_stage_kernel_p<double, EB, P>), dim3(grid), dim3(6 * EB), 0, st, b->d_insts,
+                     b->d_items + b->pstart[P], cnt, U, b->S0, b->S1, stage, b->flags);
+  return hipGetLastError();
+}
+
+template <int EB>
+hipError_t batch_launch_split(cdg2_batch* b, hipStream_t st, double* U, int stage) {
+  hipError_t e = batch_launch_p<EB, 3>(b, st, U, stage);
+  if (e == hipSuccess) e = batch_launch_p<EB, 2>(b, st, U, stage);
+  if (e == hipSuccess) e = batch_launch_p<EB, 1>(b, st, U, stage);
+  return e;
+}
+
 hipError_t batch_launch(cdg2_batch* b, hipStream_t st, double* U, int stage) {
+  if (b->order == 2) {
+    switch (b->eb) {
+      case 16: return batch_launch_split<16>(b, st, U, stage);
+      case 64: return batch_launch_split<64>(b, st, U, stage);
+      default: return batch_launch_split<32>(b, st, U, stage);
+    }
+  }
   switch (b->eb) {
     case 16: return batch_launch_eb<16>(b, st, U, stage);
     case 64: return batch_launch_eb<64>(b, st, U, stage);
@@ -1004,7 +1039,7 @@ int cdg2_batch_autotune(cdg2_batch* b, double* best) {
   int bb[3] = {32, 0, 0};
   for (int ie = 0; ie < 3 && e == hipSuccess; ++ie)
     for (int iw = 0; iw < 4 && e == hipSuccess; ++iw)
-      for (int order = 0; order < 2 && e == hipSuccess; ++order) {
+      for (int order = 0; order < 3 && e == hipSuccess; ++order) {
         b->eb = ebs[ie];
         b->nwg = wpc[iw] * ncu;
         b->order = order;
@@ -1087,7 +1122,7 @@ size_t cdg2_batch_offset(const cdg2_batch* b, int i) {
 int cdg2_batch_set_schedule(cdg2_batch* b, int eb, int nwg, int order) {
   if (!b) return fail(CDG2_EINVAL, "batch is NULL");
   if (eb != 16 && eb != 32 && eb != 64) return fail(CDG2_EINVAL, "eb must be 16, 32 or 64");
-  if (nwg < 0 || (order != 0 && order != 1)) return fail(CDG2_EINVAL, "bad schedule");
+  if (nwg < 0 || order < 0 || order > 2) return fail(CDG2_EINVAL, "bad schedule");
   b->eb = eb;
   b->nwg = nwg;
   b->order = order;

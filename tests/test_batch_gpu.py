@@ -50,7 +50,7 @@ def per_instance(insts, states, dts, nsteps):
     return outs
 
 
-@pytest.mark.parametrize("schedule", [(32, 0, 0), (16, 64, 1), (64, 8, 0), (32, 3, 1)])
+@pytest.mark.parametrize("schedule", [(32, 0, 0), (16, 64, 1), (64, 8, 0), (32, 3, 1), (32, 0, 2), (16, 5, 2)])
 @pytest.mark.parametrize("graph", [False, True])
 def test_batched_equals_per_instance(schedule, graph):
     from paper_1403_1157_amd.batch import Batch
