@@ -858,6 +858,8 @@ struct cdg2_batch {
   int* flags = nullptr;
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;
+  hipStream_t aux[2] = {nullptr, nullptr};     // order 2: the p = 2 and p = 1 launches of a stage
+  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   int eb = 32, nwg = 0, order = 0;
   int pstart[4] = {0, 0, 0, 0}, pcount[4] = {0, 0, 0, 0};   // order 2: item range per p
   hipGraph_t graph = nullptr;
@@ -938,9 +940,15 @@ hipError_t batch_launch_p(cdg2_batch* b, hipStream_t st, double* U, int stage) {
 
 template <int EB>
 hipError_t batch_launch_split(cdg2_batch* b, hipStream_t st, double* U, int stage) {
-  hipError_t e = batch_launch_p<EB, 3>(b, st, U, stage);
-  if (e == hipSuccess) e = batch_launch_p<EB, 2>(b, st, U, stage);
-  if (e == hipSuccess) e = batch_launch_p<EB, 1>(b, st, U, stage);
+  // The three orders touch disjoint instances, so their launches run side by side
+  // on forked streams and join back into st before the next stage.
+  hipError_t e = hipEventRecord(b->ev_fork, st);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->aux[k], b->ev_fork, 0);
+  if (e == hipSuccess) e = batch_launch_p<EB, 3>(b, st, U, stage);
+  if (e == hipSuccess) e = batch_launch_p<EB, 2>(b, b->aux[0], U, stage);
+  if (e == hipSuccess) e = batch_launch_p<EB, 1>(b, b->aux[1], U, stage);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventRecord(b->ev_join[k], b->aux[k]);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(st, b->ev_join[k], 0);
   return e;
 }
 
@@ -1001,7 +1009,12 @@ int cdg2_batch_create(const cdg2_config* cfgs, int count, int autotune, cdg2_bat
   }
   if (hipMemset(b->flags, 0, 64) != hipSuccess ||
       hipMemcpy(b->d_insts, b->insts.data(), count * sizeof(BatchInst), hipMemcpyHostToDevice) != hipSuccess ||
-      hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+      hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->aux[0], hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->aux[1], hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_join[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_join[1], hipEventDisableTiming) != hipSuccess) {
     cdg2_batch_destroy(b);
     return fail(CDG2_EHIP, "batch initialisation failed");
   }
@@ -1102,6 +1115,11 @@ int cdg2_batch_destroy(cdg2_batch* b) {
   if (b->S1) (void)hipFree(b->S1);
   if (b->flags) (void)hipFree(b->flags);
   if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (int k = 0; k < 2; ++k) {
+    if (b->aux[k]) (void)hipStreamDestroy(b->aux[k]);
+    if (b->ev_join[k]) (void)hipEventDestroy(b->ev_join[k]);
+  }
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   delete b;
   return CDG2_OK;
 }
