@@ -134,6 +134,22 @@ void build_tables(int p, Tables* t) {
   double l = 0.0;
   for (int i = 0; i < q; ++i) l += t->E[1][i] * t->E[1][i];
   t->liftc = l;
+  for (int i = 0; i < q; ++i) {
+    for (int r = 0; r < q; ++r) {
+      double acc = 0.0;
+      for (int k = 0; k < q; ++k) acc += t->B[i][k] * t->Bd[r][k];
+      t->Dn[r][i] = t->w[i] * acc;
+    }
+    for (int s = 0; s < 2; ++s) {
+      double a0 = 0.0, a1 = 0.0;
+      for (int k = 0; k < q; ++k) {
+        a0 += t->B[i][k] * t->E[s][k];
+        a1 += t->B[i][k] * t->dE[s][k];
+      }
+      t->Le[s][i] = t->w[i] * a0;
+      t->dLe[s][i] = t->w[i] * a1;
+    }
+  }
 }
 
 double spectral_constant_1d(int p, double pen_c, double sym) {

@@ -15,6 +15,11 @@ struct Tables {
   double dE[2][CDG2_MAXQ];          // phi_i'(0), phi_i'(1)
   double S[CDG2_MAXQ][CDG2_MAXQ];   // int_0^1 phi_i' phi_j' (exact)
   double liftc;                     // sum_i phi_i(1)^2
+  // Lagrange basis l_i of the Gauss points (nodal form of the same space):
+  // l_i = w_i sum_k phi_k(x_i) phi_k, exact because the rule integrates Q_p x Q_p.
+  double Dn[CDG2_MAXQ][CDG2_MAXQ];  // l_i'(x_q) (row q, column i)
+  double Le[2][CDG2_MAXQ];          // l_i(0), l_i(1)
+  double dLe[2][CDG2_MAXQ];         // l_i'(0), l_i'(1)
 };
 
 // q-point Gauss-Legendre rule on [0,1] (Golub-Welsch: eigen-decomposition of the
