@@ -56,7 +56,7 @@ struct EsSz {
 // instruction places lane t's chunk at LS t bytes, LS = 16 for 12- and 16-byte
 // chunks and 4 for 4-byte ones, so chunk k of thread g = (s, l) sits at byte
 // LS (g NCH + k) (a 12-byte chunk leaves 4 bytes unused).
-template <int D, int P, typename T, int EB, int NV = EsSz<D, P>::NVQ>
+template <int D, int P, typename T, int EB, int NV = EsSz<D, P>::NVQ, int XTRA = 0>
 struct EsSmem {
   using S = EsSz<D, P>;
   // 3D only: in 2D (72 to 200 bytes per (cell, species)) the staging measured no
@@ -69,7 +69,7 @@ struct EsSmem {
   static constexpr int VOL = EB * NV * S::PC;   // NV exchange slots per volume point
   static constexpr int FAC = EB * S::NFQ * S::NF;
   static constexpr int STG = STAGED ? 6 * EB * NCH * LS / (int)sizeof(T) : 0;
-  static constexpr int N0 = VOL > FAC ? VOL : FAC;
+  static constexpr int N0 = VOL > FAC + XTRA ? VOL : FAC + XTRA;   // XTRA values after the face slots
   static constexpr int N = N0 > STG ? N0 : STG;
   int nb[EB][2 * D];
   int cell[EB];
@@ -77,9 +77,9 @@ struct EsSmem {
 };
 
 // Element m of thread g's staged modes.
-template <int D, int P, typename T, int EB, int NV>
-__device__ __forceinline__ T staged(const EsSmem<D, P, T, EB, NV>& sm, int g, int m) {
-  using SM = EsSmem<D, P, T, EB, NV>;
+template <int D, int P, typename T, int EB, int NV, int XT>
+__device__ __forceinline__ T staged(const EsSmem<D, P, T, EB, NV, XT>& sm, int g, int m) {
+  using SM = EsSmem<D, P, T, EB, NV, XT>;
   constexpr int CB = SM::CB, NCH = SM::NCH, LS = SM::LS;
   const unsigned char* base = reinterpret_cast<const unsigned char*>(sm.buf);
   if constexpr (LS == CB) {   // contiguous segments
@@ -102,9 +102,9 @@ __device__ __forceinline__ T staged(const EsSmem<D, P, T, EB, NV>& sm, int g, in
 // chunks, so each load instruction reads whole cache lines of consecutive cells
 // (one lane per cell and 216-byte modes would put every lane on its own line).
 // The caller waits (vmcnt) and synchronises before reading.
-template <int D, int P, typename T, int EB, int NV>
-__device__ __forceinline__ void stage_modes(const T* U, size_t SE, int E, EsSmem<D, P, T, EB, NV>& sm, int tid) {
-  using SM = EsSmem<D, P, T, EB, NV>;
+template <int D, int P, typename T, int EB, int NV, int XT>
+__device__ __forceinline__ void stage_modes(const T* U, size_t SE, int E, EsSmem<D, P, T, EB, NV, XT>& sm, int tid) {
+  using SM = EsSmem<D, P, T, EB, NV, XT>;
   constexpr int NM = EsSz<D, P>::NM, NT = 6 * EB, CB = SM::CB, NCH = SM::NCH;
   static_assert(SM::BYTES % CB == 0, "chunking");
   constexpr int PER = EB * NCH;                 // chunks per species

@@ -176,8 +176,10 @@ __device__ __forceinline__ void nd_tapply3(const T* in, T* out) {
 // 4..6 with F1 (weighted, / h_a), 7..9 with F2 and 10 with the alpha term.
 constexpr int ND_NVQ = 15;
 
+// After the face slots: each thread's face jump and derivative sum (2 x NF
+// values), parked there through the face point pass.
 template <int P, typename T, int EB>
-using NdSmem = EsSmem<3, P, T, EB, ND_NVQ>;
+using NdSmem = EsSmem<3, P, T, EB, ND_NVQ, 6 * EB * 2 * (P + 1) * (P + 1)>;
 
 // Workgroup barrier that is also a scheduling fence: no instruction moves across
 // it, so the compiler cannot start a later layer's or face's arithmetic early and
@@ -196,7 +198,7 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
   constexpr int Q = S::Q, NM = S::NM, NF = S::NF, NFACE = S::NFACE, PC = S::PC;
   constexpr int NVQ = ND_NVQ, NT = 6 * EB;
   static_assert(NdSmem<P, T, EB>::STAGED, "3D staging");
-  static_assert(EB * NVQ * PC <= NdSmem<P, T, EB>::N && EB * S::NFQ * NF <= NdSmem<P, T, EB>::N &&
+  static_assert(EB * NVQ * PC <= NdSmem<P, T, EB>::N && EB * S::NFQ * NF + NT * 2 * NF <= NdSmem<P, T, EB>::N &&
                     NT * NM <= NdSmem<P, T, EB>::N,
                 "LDS union");
   const Tables& tb = prm.tb;
@@ -393,18 +395,6 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
     // end values come from the run-time tables: selected among compile-time
     // constants, the compiler formed both sides' products and kept them live.
     T uo[NF], duo[NF], un[NF], dun[NF];
-#pragma unroll
-    for (int t = 0; t < NF; ++t) {
-      T a0 = T(0), a1 = T(0);
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const T x = v[face_mode<D, Q>(a, i, t)];
-        a0 += T(tb.Le[sg][i]) * x;
-        a1 += T(tb.dLe[sg][i]) * x;
-      }
-      uo[t] = a0;
-      duo[t] = a1 * T(g.ih[a]);
-    }
     T w0;   // neighbour mean (mode 0); un, dun are its fluctuation's traces
     {
       // a boundary face reads the own cell (in range) and weighs it by zero
@@ -428,6 +418,18 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
       nd_tapply2<Q, false, T>(md, dun);
       w0 = un_src[0] * inner;
     }
+#pragma unroll
+    for (int t = 0; t < NF; ++t) {
+      T a0 = T(0), a1 = T(0);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const T x = v[face_mode<D, Q>(a, i, t)];
+        a0 += T(tb.Le[sg][i]) * x;
+        a1 += T(tb.dLe[sg][i]) * x;
+      }
+      uo[t] = a0;
+      duo[t] = a1 * T(g.ih[a]);
+    }
     // publish the point values of the face point pass (the exchange slots overlay
     // the volume slots: everyone has finished reading them)
     if (fvslot >= 0) {
@@ -443,6 +445,14 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
         Fx[(el * 14 + dslot) * NF + t] = duo[t];
         Fx[(el * 14 + dslot + 3) * NF + t] = dun[t];
       }
+    }
+    // the jump and the derivative sum wait in LDS during the point pass (no
+    // registers held through it)
+    T* park = sm.buf + EB * S::NFQ * NF + tid * 2 * NF;
+#pragma unroll
+    for (int t = 0; t < NF; ++t) {
+      park[t] = (m0 - w0) + (uo[t] - un[t]);
+      park[NF + t] = duo[t] + dun[t];
     }
     nd_sync();
     // face point pass
@@ -502,25 +512,25 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
       const T pen = T(g.pen_c * tb.liftc * g.ih[a]) * as;
       const T hs = T(0.5 * g.sym) * as * so * T(g.ih[a]);
       const bool in = nb >= 0;
-      const T dw = T(diss ? 1 : 0), f1w = T(s == S_N1 ? 1 : 0), f2w = T(s == S_N2 ? 1 : 0);
-      const int bsl = s == S_N2 ? 4 : s == S_C2 ? 5 : 3;   // inflow slot (n1 3, n2 4, c2 5)
-      const T bw = T(s == S_N1 || s == S_N2 || s == S_C2 ? 1 : 0);
-      T G[NF], H[NF];
+      const T dw = T(diss ? 1 : 0);
+      // the one flux slot this species adds: interior n1 F1 (1), n2 F2 (2);
+      // boundary inflow n1 (3), n2 (4), c2 (5); weight 0 for the others
+      const int ksl = in ? (s == S_N2 ? 2 : 1) : (s == S_N2 ? 4 : s == S_C2 ? 5 : 3);
+      const T kw = T(in ? (s == S_N1 || s == S_N2 ? 1 : 0) : (s == S_N1 || s == S_N2 || s == S_C2 ? 1 : 0));
+      const T li = T(in ? 1 : 0);   // linear face terms on interior faces only
+      const T le0 = T(tb.Le[sg][0]), le1 = T(tb.Le[sg][1]), dle0 = T(tb.dLe[sg][0]), dle1 = T(tb.dLe[sg][1]);
+      const T le2 = T(tb.Le[sg][Q - 1]), dle2 = T(tb.dLe[sg][Q - 1]);
+      const T* park = sm.buf + EB * S::NFQ * NF + tid * 2 * NF;
 #pragma unroll
       for (int t = 0; t < NF; ++t) {
+        const T jm = park[t], sd = park[NF + t];
         const T wa = ar * T(ct.w[t % Q] * ct.w[t / Q]);
-        const T jm = (m0 - w0) + (uo[t] - un[t]);
-        const T gi = so * T(0.5) * as * (duo[t] + dun[t]) - (pen + dw * x[t]) * jm + f1w * x[NF + t] +
-                     f2w * x[2 * NF + t];
-        const T gb = bw * x[bsl * NF + t];
-        G[t] = wa * (in ? gi : gb);
-        H[t] = in ? wa * (hs * jm) : T(0);
-      }
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const T le = T(tb.Le[sg][i]), dle = T(tb.dLe[sg][i]);
-#pragma unroll
-        for (int t = 0; t < NF; ++t) R[face_mode<D, Q>(a, i, t)] += le * G[t] + dle * H[t];
+        const T gv = li * (so * T(0.5) * as * sd - (pen + dw * x[t]) * jm) + kw * x[ksl * NF + t];
+        const T G = wa * gv, H = li * wa * (hs * jm);
+        // spread at once onto the normal line through the point
+        R[face_mode<D, Q>(a, 0, t)] += le0 * G + dle0 * H;
+        if (Q == 3) R[face_mode<D, Q>(a, 1, t)] += le1 * G + dle1 * H;
+        R[face_mode<D, Q>(a, Q - 1, t)] += le2 * G + dle2 * H;
       }
     }
   }
