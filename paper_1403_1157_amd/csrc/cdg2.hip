@@ -14,8 +14,6 @@
 #include "cfl_kernel.hpp"
 #include "adj_kernel.hpp"
 #include "batch_kernel.hpp"
-#include <type_traits>
-
 #include "es_kernel.hpp"
 #include "nodal_kernel.hpp"
 #include "vec_kernel.hpp"
@@ -153,10 +151,8 @@ hipError_t launch_op(cdg2_handle* h, const void* U, const void* U0, void* out, d
                      double cb, int stage) {
   constexpr int EB = EsCfg<D, P>::EB;
   int nb = (h->geo.E + EB - 1) / EB;
-  // nodal form for FP64 3D p <= 2; 3D p = 3 keeps the modal kernel (register
-  // budget), and so does FP32, whose jumps the modal kernel forms mode by mode
-  // (the nodal form takes them as differences of two rounded traces)
-  if constexpr (D == 3 && P <= 2 && std::is_same<T, double>::value) {
+  // nodal form for 3D p <= 2; 3D p = 3 keeps the modal kernel (register budget)
+  if constexpr (D == 3 && P <= 2) {
     hipLaunchKernelGGL((nd_kernel<P, T, EB>), dim3(nb), dim3(6 * EB), 0, h->stream, h->dprm, (const T*)U,
                        (const T*)U0, (T*)out, (T)dt, (T)ca, (T)cb, stage, h->flags);
   } else {

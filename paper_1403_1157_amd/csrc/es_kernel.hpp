@@ -1,5 +1,5 @@
-// CDG2 operator kernel, one thread per (cell, species), in the modal basis (2D,
-// FP32, 3D p = 3; 3D FP64 p <= 2 runs the nodal form of nodal_kernel.hpp).
+// CDG2 operator kernel, one thread per (cell, species), in the modal basis (2D
+// and 3D p = 3; 3D p <= 2 runs the nodal form of nodal_kernel.hpp).
 //
 // Per cell (Section 3.1) the residual is
 //   volume:   int_K (F(U) - A grad U) : grad phi + S(U) phi
