@@ -139,6 +139,50 @@ __device__ __forceinline__ void stage_modes(const T* U, size_t SE, int E, EsSmem
 
 __device__ __forceinline__ void wait_staged() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// Coalesced store of the workgroup's results, which sit in buf as
+// [species][cell][mode] (6 EB NM values): out = buf (+ ca U0 for the stage
+// combination).  The U0 values of up to 16 of the thread's slots are loaded
+// before the first one is used, so the loads overlap instead of each costing a
+// full memory latency.
+template <typename T, int EB, int NM>
+__device__ __forceinline__ void store_results(const int* cell, const T* buf, const T* U0, T* out, size_t SE,
+                                              T ca, bool combine, int tid, int& flag) {
+  constexpr int NT = 6 * EB, TOT = 6 * EB * NM, PERS = EB * NM, IT = (TOT + NT - 1) / NT;
+  constexpr int CH = IT < 16 ? IT : 16;
+  auto index = [&](int i, bool& ok) -> size_t {
+    const int ii = i < TOT ? i : 0;
+    const int sp = ii / PERS, rem = ii - sp * PERS;
+    const int l = rem / NM, m = rem - l * NM;
+    const int cl = cell[l];
+    ok = i < TOT && cl >= 0;
+    return sp * SE + (size_t)(cl >= 0 ? cl : 0) * NM + m;   // in range in every case
+  };
+#pragma unroll
+  for (int k0 = 0; k0 < IT; k0 += CH) {
+    T u0[CH];
+    if (combine) {
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        bool ok;
+        const size_t gi = index(tid + (k0 + k) * NT, ok);
+        u0[k] = ok && k0 + k < IT ? U0[gi] : T(0);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      if (k0 + k >= IT) break;
+      const int i = tid + (k0 + k) * NT;
+      bool ok;
+      const size_t gi = index(i, ok);
+      if (!ok) continue;
+      T val = buf[i];
+      if (combine) val += ca * u0[k];
+      if (!isfinite(val)) flag |= FLAG_NONFINITE;
+      out[gi] = val;
+    }
+  }
+}
+
 // (D-1)-dimensional tensor contraction of NF values (tangential / layer axes).
 template <int D, int Q, bool TR, typename T>
 __device__ __forceinline__ void tapply_lo(const T* in, T* out, const double (*M0)[CDG2_MAXQ],
@@ -563,18 +607,7 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
 #pragma unroll
     for (int m = 0; m < NM; ++m) sm.buf[tid * NM + m] = stage == 0 ? R[m] * ivol : cb * (u[m] + dt * (R[m] * ivol));
     __syncthreads();
-    constexpr int TOT = 6 * EB * NM, PERS = EB * NM;
-    for (int i = tid; i < TOT; i += NT) {
-      const int sp = i / PERS, rem = i - sp * PERS;
-      const int l = rem / NM, m = rem - l * NM;
-      const int cl = sm.cell[l];
-      if (cl < 0) continue;
-      const size_t gi = sp * SE + (size_t)cl * NM + m;
-      T v = sm.buf[i];
-      if (stage != 0 && ca != T(0)) v += ca * U0[gi];
-      if (!isfinite(v)) flag |= FLAG_NONFINITE;
-      out[gi] = v;
-    }
+    store_results<T, EB, NM>(sm.cell, sm.buf, U0, out, SE, ca, stage != 0 && ca != T(0), tid, flag);
   } else if (live) {
     const T ivol = T(1.0 / g.vol);
     T* dst = out + s * SE + (size_t)e * NM;

@@ -563,18 +563,7 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
     for (int m = 0; m < NM; ++m) sm.buf[tid * NM + m] = stage == 0 ? y[m] : cb * y[m];
   }
   nd_sync();
-  constexpr int TOT = 6 * EB * NM, PERS = EB * NM;
-  for (int i = tid; i < TOT; i += NT) {
-    const int sp = i / PERS, rem = i - sp * PERS;
-    const int l = rem / NM, m = rem - l * NM;
-    const int cl = sm.cell[l];
-    if (cl < 0) continue;
-    const size_t gi = sp * SE + (size_t)cl * NM + m;
-    T val = sm.buf[i];
-    if (stage != 0 && ca != T(0)) val += ca * U0[gi];
-    if (!isfinite(val)) flag |= FLAG_NONFINITE;
-    out[gi] = val;
-  }
+  store_results<T, EB, NM>(sm.cell, sm.buf, U0, out, SE, ca, stage != 0 && ca != T(0), tid, flag);
   if (flag) atomicOr(flags, flag);
 }
 
