@@ -140,46 +140,62 @@ __device__ __forceinline__ void stage_modes(const T* U, size_t SE, int E, EsSmem
 __device__ __forceinline__ void wait_staged() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // Coalesced store of the workgroup's results, which sit in buf as
-// [species][cell][mode] (6 EB NM values): out = buf (+ ca U0 for the stage
-// combination).  The U0 values of up to 16 of the thread's slots are loaded
-// before the first one is used, so the loads overlap instead of each costing a
-// full memory latency.
+// [species][cell][mode] (6 EB NM values): thread tid stores slots
+// i = tid + k 6EB, out = buf (+ ca U0 for the stage combination).  The U0 values
+// of a chunk of CH slots are all loaded before the first one is used, so the
+// loads overlap instead of each costing a full memory latency.
+template <int EB, int NM>
+__device__ __forceinline__ size_t slot_index(const int* cell, size_t SE, int i, bool& ok) {
+  constexpr int TOT = 6 * EB * NM, PERS = EB * NM;
+  const int ii = i < TOT ? i : 0;
+  const int sp = ii / PERS, rem = ii - sp * PERS;
+  const int l = rem / NM, m = rem - l * NM;
+  const int cl = cell[l];
+  ok = i < TOT && cl >= 0;
+  return sp * SE + (size_t)(cl >= 0 ? cl : 0) * NM + m;   // in range in every case
+}
+
+template <int EB, int NM>
+constexpr int store_slots() { return (6 * EB * NM + 6 * EB - 1) / (6 * EB); }
+
+template <typename T, int EB, int NM, int CH>
+__device__ __forceinline__ void load_u0_chunk(const int* cell, const T* U0, size_t SE, int tid, int k0, T* u0) {
+  constexpr int NT = 6 * EB, IT = store_slots<EB, NM>();
+#pragma unroll
+  for (int k = 0; k < CH; ++k) {
+    bool ok;
+    const size_t gi = slot_index<EB, NM>(cell, SE, tid + (k0 + k) * NT, ok);
+    u0[k] = ok && k0 + k < IT ? U0[gi] : T(0);
+  }
+}
+
+template <typename T, int EB, int NM, int CH>
+__device__ __forceinline__ void store_chunk(const int* cell, const T* buf, const T* u0, T* out, size_t SE, T ca,
+                                            bool combine, int tid, int k0, int& flag) {
+  constexpr int NT = 6 * EB, IT = store_slots<EB, NM>();
+#pragma unroll
+  for (int k = 0; k < CH; ++k) {
+    if (k0 + k >= IT) break;
+    const int i = tid + (k0 + k) * NT;
+    bool ok;
+    const size_t gi = slot_index<EB, NM>(cell, SE, i, ok);
+    if (!ok) continue;
+    T val = buf[i];
+    if (combine) val += ca * u0[k];
+    if (!isfinite(val)) flag |= FLAG_NONFINITE;
+    out[gi] = val;
+  }
+}
+
 template <typename T, int EB, int NM>
 __device__ __forceinline__ void store_results(const int* cell, const T* buf, const T* U0, T* out, size_t SE,
                                               T ca, bool combine, int tid, int& flag) {
-  constexpr int NT = 6 * EB, TOT = 6 * EB * NM, PERS = EB * NM, IT = (TOT + NT - 1) / NT;
-  constexpr int CH = IT < 16 ? IT : 16;
-  auto index = [&](int i, bool& ok) -> size_t {
-    const int ii = i < TOT ? i : 0;
-    const int sp = ii / PERS, rem = ii - sp * PERS;
-    const int l = rem / NM, m = rem - l * NM;
-    const int cl = cell[l];
-    ok = i < TOT && cl >= 0;
-    return sp * SE + (size_t)(cl >= 0 ? cl : 0) * NM + m;   // in range in every case
-  };
+  constexpr int IT = store_slots<EB, NM>(), CH = IT < 16 ? IT : 16;
 #pragma unroll
   for (int k0 = 0; k0 < IT; k0 += CH) {
     T u0[CH];
-    if (combine) {
-#pragma unroll
-      for (int k = 0; k < CH; ++k) {
-        bool ok;
-        const size_t gi = index(tid + (k0 + k) * NT, ok);
-        u0[k] = ok && k0 + k < IT ? U0[gi] : T(0);
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < CH; ++k) {
-      if (k0 + k >= IT) break;
-      const int i = tid + (k0 + k) * NT;
-      bool ok;
-      const size_t gi = index(i, ok);
-      if (!ok) continue;
-      T val = buf[i];
-      if (combine) val += ca * u0[k];
-      if (!isfinite(val)) flag |= FLAG_NONFINITE;
-      out[gi] = val;
-    }
+    if (combine) load_u0_chunk<T, EB, NM, CH>(cell, U0, SE, tid, k0, u0);
+    store_chunk<T, EB, NM, CH>(cell, buf, u0, out, SE, ca, combine, tid, k0, flag);
   }
 }
 

@@ -536,6 +536,12 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
   }
 
   // ---- back to modes: M^{-1}, stage combination, coalesced store ------------------------
+  // the u0 values this thread will store are requested first, so that their
+  // latency overlaps the transform back to modes
+  constexpr int IT = store_slots<EB, NM>();
+  const bool combine = stage != 0 && ca != T(0);
+  T u0[IT];
+  if (combine) load_u0_chunk<T, EB, NM, IT>(sm.cell, U0, SE, tid, 0, u0);
   {
     const T ivol = T(1.0 / g.vol);
     T z[NM], y[NM];
@@ -563,7 +569,7 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
     for (int m = 0; m < NM; ++m) sm.buf[tid * NM + m] = stage == 0 ? y[m] : cb * y[m];
   }
   nd_sync();
-  store_results<T, EB, NM>(sm.cell, sm.buf, U0, out, SE, ca, stage != 0 && ca != T(0), tid, flag);
+  store_chunk<T, EB, NM, IT>(sm.cell, sm.buf, u0, out, SE, ca, combine, tid, 0, flag);
   if (flag) atomicOr(flags, flag);
 }
 
