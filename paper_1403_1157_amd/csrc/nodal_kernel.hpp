@@ -215,13 +215,14 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
 
   // ---- own modes -> nodal values --------------------------------------------------
   T v[NM], R[NM], m0;
+  if (tid < EB) sm.cell[tid] = e0 + tid < E ? cell_of<D>(g, e0 + tid) : -1;
+  nd_sync();
+  stage_modes<D, P, T, EB>(U, SE, E, sm, tid);
+  // the neighbour table is built while the modes are in flight
   for (int it = tid; it < EB * NFACE; it += NT) {
     int l = it / NFACE, f = it % NFACE;
     sm.nb[l][f] = e0 + l < E ? neighbour<D>(g, cell_of<D>(g, e0 + l), f) : -3;
   }
-  if (tid < EB) sm.cell[tid] = e0 + tid < E ? cell_of<D>(g, e0 + tid) : -1;
-  nd_sync();
-  stage_modes<D, P, T, EB>(U, SE, E, sm, tid);
   wait_staged();
   nd_sync();
   {
