@@ -233,3 +233,63 @@ def reduced_3d_modes(n, p: int, key: tuple = (6,)) -> np.ndarray:
     U[2, :, 0] = 0.05
     U[2] += 0.5 * bump
     return U
+
+
+def kuhn_mesh(nx: int, ny: int, jitter: float = 0.0, key: tuple = (7,)):
+    """Triangle mesh of [0,1]^2: each of nx x ny squares split along its rising
+    diagonal, periodic in x, walls y = 0 (Gamma1) and y = 1 (Gamma2).  Optional
+    seeded jitter moves every vertex (x, and y off the walls) by up to `jitter`
+    cell widths, which makes the mesh non-uniform (unequal triangles).
+
+    Returns xy [E, 3, 2] (vertex coordinates per element, counter-clockwise,
+    periodic images unwrapped), nbr [E, 3] (element across edge j, from vertex j
+    to vertex j+1, or -1 on Gamma1, -2 on Gamma2) and nbe [E, 3] (that edge's
+    index in the neighbour)."""
+    hx, hy = 1.0 / nx, 1.0 / ny
+    rng = rng_for(*key)
+    dx = rng.uniform(-jitter, jitter, size=(nx, ny + 1)) * hx
+    dy = rng.uniform(-jitter, jitter, size=(nx, ny + 1)) * hy
+    dy[:, 0] = 0.0
+    dy[:, ny] = 0.0
+
+    def vert(i, j):
+        ii = i % nx
+        return (i * hx + dx[ii, j], j * hy + dy[ii, j]), ii + nx * j
+
+    xy, vid = [], []
+    for j in range(ny):
+        for i in range(nx):
+            (a, va), (b, vb), (c, vc), (d, vd) = vert(i, j), vert(i + 1, j), vert(i + 1, j + 1), vert(i, j + 1)
+            xy.append([a, b, c])
+            vid.append([va, vb, vc])
+            xy.append([a, c, d])
+            vid.append([va, vc, vd])
+    xy = np.array(xy, dtype=np.float64)
+    E = len(vid)
+    nbr = np.full((E, 3), -9, dtype=np.int32)
+    nbe = np.full((E, 3), -1, dtype=np.int32)
+    owner = {}
+    for e in range(E):
+        for k in range(3):
+            a, b = vid[e][k], vid[e][(k + 1) % 3]
+            key2 = (min(a, b), max(a, b))
+            if key2 in owner:
+                f, kk = owner.pop(key2)
+                nbr[e, k], nbe[e, k] = f, kk
+                nbr[f, kk], nbe[f, kk] = e, k
+            else:
+                owner[key2] = (e, k)
+    for (a, b), (e, k) in owner.items():
+        nbr[e, k] = -1 if a < nx and b < nx else -2
+    assert (nbr != -9).all()
+    return xy, nbr, nbe
+
+
+def tri_modes(E: int, k: int, key: tuple = (8,), amp: float = 0.02) -> np.ndarray:
+    """Random modal coefficients U[6, E, (k+1)(k+2)/2] of a positive field on a
+    triangle mesh: cell means in [0.3, 0.7], the other modes within +-amp."""
+    rng = rng_for(*key)
+    nb = (k + 1) * (k + 2) // 2
+    U = rng.uniform(-amp, amp, size=(6, E, nb))
+    U[:, :, 0] = rng.uniform(0.3, 0.7, size=(6, E))
+    return U

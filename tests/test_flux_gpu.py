@@ -29,7 +29,8 @@ def gpu_op(cfg, precision="fp64"):
 
 CASES = [("br2", 3.0, 2, (5, 4), 2), ("ip", 5.0, 2, (5, 4), 2), ("bo", 0.0, 2, (5, 4), 2),
          ("ip", 0.0, 2, (4, 5), 4), ("bo", 0.0, 2, (6, 3), 1), ("br2", 0.0, 3, (3, 3, 2), 2),
-         ("ip", 7.0, 3, (3, 2, 3), 1), ("bo", 0.0, 3, (2, 3, 3), 3)]
+         ("ip", 7.0, 3, (3, 2, 3), 1), ("bo", 0.0, 3, (2, 3, 3), 3), ("ip", 6.0, 3, (2, 3, 4), 2),
+         ("bo", 0.0, 3, (3, 4, 2), 2), ("bo", 0.0, 3, (3, 2, 2), 1)]
 
 
 @pytest.mark.parametrize("flux,eta,dim,n,p", CASES)
