@@ -283,6 +283,39 @@ def bench_fluxes(n=(128, 128), p=2, a=0.05, T=0.02):
             "fluxes": out}
 
 
+def bench_triangles(n=256, steps=100, reps=200):
+    """Unstructured P_k triangles: an n x n Kuhn mesh of [0,1]^2 with jittered
+    vertices (2 n^2 triangles), P1 and P2; operator applications and an SSP-RK3
+    run.  Algorithmic bytes as for the Cartesian grids (16 B/DOF per apply,
+    64 B/DOF per step, state only)."""
+    import torch
+
+    from paper_1403_1157_amd import inputs
+    from paper_1403_1157_amd.cdg2 import TriOperator
+
+    xy, nbr, nbe = inputs.kuhn_mesh(n, n, 0.2, (14,))
+    out = {}
+    for k in (1, 2):
+        op = TriOperator(k, xy, nbr, nbe, inputs.base_coeffs())
+        U0 = torch.from_numpy(inputs.tri_modes(len(xy), k, key=(15, k))).cuda()
+        dof = U0.numel()
+        F = torch.empty_like(U0)
+        op.apply(U0, F)
+        op.sync()
+        us_apply = 1e3 * time_ms(lambda: op.apply(U0, F), reps)
+        U = U0.clone()
+        op.rk_step(U, 1e-6, 2)
+        op.sync()
+        U = U0.clone()
+        us_step = 1e3 * time_ms(lambda: op.rk_step(U, 1e-6, steps)) / steps
+        op.sync()
+        out[f"p{k}"] = {"us_per_apply": round(us_apply, 2), "apply_frac": round(16 * dof / us_apply / 1e3 / HBM_PEAK_GBS, 4),
+                        "us_per_step": round(us_step, 2), "step_frac": round(64 * dof / us_step / 1e3 / HBM_PEAK_GBS, 4),
+                        "gdof_s": round(3 * dof / us_step / 1e3, 3)}
+    return {"workload": f"{n}x{n} Kuhn mesh, jittered ({2 * n * n} triangles), {reps} applies and a "
+                        f"{steps}-step SSP-RK3 run", **out}
+
+
 def bench_2d(reps=1000, steps=100):
     """The 256^2 workloads with Q2 and Q4: reps operator applications replayed
     from one captured HIP graph, and a steps-long SSP-RK3 run."""
@@ -457,6 +490,7 @@ def main():
         line["adjoint"] = bench_adjoint()
         line["implicit"] = bench_implicit()
         line["fluxes"] = bench_fluxes()
+        line["triangles"] = bench_triangles()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(dim, n, p, key, dof)
     print(json.dumps(line), flush=True)

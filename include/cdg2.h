@@ -276,6 +276,48 @@ int cdg2_batch_rk(cdg2_batch* b, void* U_packed, const size_t* offsets, const do
 /* Wait for the batch's stream; report non-finite / domain conditions. */
 int cdg2_batch_sync(cdg2_batch* b);
 
+/* ---- unstructured triangle meshes (P_k, k = 1, 2; FP64) -------------------------
+ *
+ * The same six-species operator on a conforming triangle mesh (Section 3.1 on
+ * simplices, the element type of the paper's own runs): full P_k per triangle
+ * with an orthonormal basis (phi_0 = 1, so mode 0 is the element mean and
+ * M_K = |K| I; the reference basis is the Gram-Schmidt orthonormalisation, for
+ * the mean over the reference triangle (0,0), (1,0), (0,1), of the monomials
+ * 1, xi, eta, xi^2, xi eta, eta^2 in that order), collapsed Gauss rules of k + 1
+ * points per direction on the triangle and k + 1 Gauss points per edge, the LLF
+ * and CDG2 fluxes (lifting on K^-: the smaller triangle of an edge, ties to the
+ * lower element index; chi_e = 3/2) and the inflow fluxes of eqs. (7)-(9) on the
+ * edges coded Gamma1 / Gamma2.  State layout: U[6][E][(k+1)(k+2)/2] doubles,
+ * species n1, n2, n3, c1, c2, c3.
+ *
+ * Mesh (HOST arrays, copied at create):
+ *   xy   [E][3][2]  vertex coordinates of each element, counter-clockwise (an
+ *                   element that is not gives CDG2_EINVAL); periodic images are
+ *                   given unwrapped, so each element is a proper triangle;
+ *   nbr  [E][3]     element across edge j (from vertex j to vertex j+1), or -1
+ *                   (Gamma1) / -2 (Gamma2);
+ *   nbe  [E][3]     that edge's index in the neighbour (ignored on boundaries).
+ * The tables must be reciprocal (nbr[nbr[e][j]][nbe[e][j]] == e and
+ * nbe[nbr[e][j]][nbe[e][j]] == j), else CDG2_EINVAL.  Gamma_{1,in} is the set of
+ * Gamma1 points with x in [gamma1_in_lo, gamma1_in_hi]. */
+typedef struct cdg2_tri cdg2_tri;
+int cdg2_tri_create(int order, int n_elements, const double* xy, const int* nbr, const int* nbe,
+                    const cdg2_coeffs* coeffs, double gamma1_in_lo, double gamma1_in_hi, cdg2_tri** out);
+int cdg2_tri_destroy(cdg2_tri* t);
+/* Stream of all later launches (NULL: the default stream). */
+int cdg2_tri_set_stream(cdg2_tri* t, void* stream);
+/* 6 E (k+1)(k+2)/2. */
+size_t cdg2_tri_num_dofs(const cdg2_tri* t);
+/* F = M^-1 L_h(U) (DEVICE arrays of cdg2_tri_num_dofs doubles, not overlapping).
+ * Asynchronous; see cdg2_tri_sync. */
+int cdg2_tri_apply_operator(cdg2_tri* t, const double* U, double* F);
+/* nsteps SSP-RK3 steps of size dt on U in place (DEVICE), the stage combination
+ * fused into the operator kernel as for the Cartesian grids. */
+int cdg2_tri_rk_step(cdg2_tri* t, double* U, double dt, int nsteps);
+/* Wait for the stream; report non-finite / domain conditions (CDG2_ENONFINITE,
+ * CDG2_EDOMAIN) raised by the launches since the last call. */
+int cdg2_tri_sync(cdg2_tri* t);
+
 /* Thread-local message of the last error. */
 const char* cdg2_last_error(void);
 

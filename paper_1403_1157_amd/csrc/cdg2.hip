@@ -16,6 +16,7 @@
 #include "batch_kernel.hpp"
 #include "es_kernel.hpp"
 #include "nodal_kernel.hpp"
+#include "tri_kernel.hpp"
 #include "vec_kernel.hpp"
 #include "tables.cpp"
 
@@ -1217,6 +1218,304 @@ int cdg2_batch_sync(cdg2_batch* b) {
   int f = 0;
   HIP_TRY(hipMemcpy(&f, b->flags, sizeof f, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemset(b->flags, 0, sizeof(int)));
+  if (f & FLAG_NONFINITE) return fail(CDG2_ENONFINITE, "non-finite value written to a state buffer");
+  if (f & FLAG_DOMAIN) return fail(CDG2_EDOMAIN, "c + chi^th <= 0 in a chemotactic sensitivity");
+  return CDG2_OK;
+}
+
+}  // extern "C"
+
+// ---- unstructured triangle meshes (P_k) -------------------------------------------
+
+struct cdg2_tri {
+  int k = 1, E = 0, nb = 3;
+  size_t ndof = 0;
+  TriParams hp{};
+  TriParams* dprm = nullptr;
+  double* geo = nullptr;   // jit, area, len, nrm, xv (one allocation)
+  int* topo = nullptr;     // nbr, nbe, minus
+  double* stage[2] = {nullptr, nullptr};
+  int* flags = nullptr;
+  hipStream_t stream = nullptr;
+};
+
+namespace {
+
+// Orthonormal basis of P_k on the reference triangle for the mean, by modified
+// Gram-Schmidt of the monomials xi^a eta^b (total degree, then power of eta),
+// with a collapsed Gauss rule exact for the products; then its values and
+// gradients at the volume and edge points of the operator's rules.
+void build_tri_tables(int k, TriTables* t) {
+  std::memset(t, 0, sizeof(TriTables));
+  int pw[TRI_MAXB][2], nb = 0;
+  for (int d = 0; d <= k; ++d)
+    for (int b = 0; b <= d; ++b) {
+      pw[nb][0] = d - b;
+      pw[nb][1] = b;
+      ++nb;
+    }
+  auto mono = [&](double x, double y, double* v, double* gx, double* gy) {
+    for (int m = 0; m < nb; ++m) {
+      const int a = pw[m][0], b = pw[m][1];
+      v[m] = std::pow(x, a) * std::pow(y, b);
+      gx[m] = a > 0 ? a * std::pow(x, a - 1) * std::pow(y, b) : 0.0;
+      gy[m] = b > 0 ? b * std::pow(x, a) * std::pow(y, b - 1) : 0.0;
+    }
+  };
+  auto duffy = [](int q, std::vector<double>& px, std::vector<double>& py, std::vector<double>& pw2) {
+    double x[CDG2_MAXQ + 4], w[CDG2_MAXQ + 4];
+    gauss_rule01(q, x, w);
+    px.clear(); py.clear(); pw2.clear();
+    for (int i = 0; i < q; ++i)
+      for (int j = 0; j < q; ++j) {
+        px.push_back(x[i]);
+        py.push_back(x[j] * (1.0 - x[i]));
+        pw2.push_back(2.0 * w[i] * w[j] * (1.0 - x[i]));   // for the mean (sum 1)
+      }
+  };
+  // Gram matrix of the monomials
+  std::vector<double> px, py, pwt;
+  duffy(k + 3, px, py, pwt);
+  double G[TRI_MAXB][TRI_MAXB] = {};
+  for (size_t n = 0; n < px.size(); ++n) {
+    double v[TRI_MAXB], gx[TRI_MAXB], gy[TRI_MAXB];
+    mono(px[n], py[n], v, gx, gy);
+    for (int a = 0; a < nb; ++a)
+      for (int b = 0; b < nb; ++b) G[a][b] += pwt[n] * v[a] * v[b];
+  }
+  auto ip = [&](const double* x, const double* y) {
+    double r = 0.0;
+    for (int a = 0; a < nb; ++a)
+      for (int b = 0; b < nb; ++b) r += x[a] * G[a][b] * y[b];
+    return r;
+  };
+  double C[TRI_MAXB][TRI_MAXB] = {};
+  for (int j = 0; j < nb; ++j) {
+    double c[TRI_MAXB] = {};
+    c[j] = 1.0;
+    for (int i = 0; i < j; ++i) {
+      const double r = ip(C[i], c);
+      for (int m = 0; m < nb; ++m) c[m] -= r * C[i][m];
+    }
+    const double nrm = std::sqrt(ip(c, c));
+    for (int m = 0; m < nb; ++m) C[j][m] = c[m] / nrm;
+  }
+  auto basis = [&](double x, double y, double* v, double* g0, double* g1) {
+    double mv[TRI_MAXB], mx[TRI_MAXB], my[TRI_MAXB];
+    mono(x, y, mv, mx, my);
+    for (int j = 0; j < nb; ++j) {
+      double a = 0.0, b = 0.0, c2 = 0.0;
+      for (int m = 0; m < nb; ++m) {
+        a += C[j][m] * mv[m];
+        b += C[j][m] * mx[m];
+        c2 += C[j][m] * my[m];
+      }
+      v[j] = a;
+      g0[j] = b;
+      g1[j] = c2;
+    }
+  };
+  duffy(k + 1, px, py, pwt);
+  for (size_t q = 0; q < px.size(); ++q) {
+    double v[TRI_MAXB], g0[TRI_MAXB], g1[TRI_MAXB];
+    basis(px[q], py[q], v, g0, g1);
+    for (int j = 0; j < nb; ++j) {
+      t->Bv[q][j] = v[j];
+      t->Bg[q][j][0] = g0[j];
+      t->Bg[q][j][1] = g1[j];
+    }
+    t->wv[q] = pwt[q];
+  }
+  double es[CDG2_MAXQ], ew[CDG2_MAXQ];
+  gauss_rule01(k + 1, es, ew);
+  const double VX[3] = {0.0, 1.0, 0.0}, VY[3] = {0.0, 0.0, 1.0};
+  for (int p = 0; p <= k; ++p) {
+    t->s[p] = es[p];
+    t->ws[p] = ew[p];
+  }
+  for (int e = 0; e < 3; ++e)
+    for (int p = 0; p <= k; ++p) {
+      const double x = VX[e] + es[p] * (VX[(e + 1) % 3] - VX[e]);
+      const double y = VY[e] + es[p] * (VY[(e + 1) % 3] - VY[e]);
+      double v[TRI_MAXB], g0[TRI_MAXB], g1[TRI_MAXB];
+      basis(x, y, v, g0, g1);
+      for (int j = 0; j < nb; ++j) {
+        t->Be[e][p][j] = v[j];
+        t->Bge[e][p][j][0] = g0[j];
+        t->Bge[e][p][j][1] = g1[j];
+      }
+    }
+}
+
+void tri_free(cdg2_tri* t) {
+  if (t->dprm) (void)hipFree(t->dprm);
+  if (t->geo) (void)hipFree(t->geo);
+  if (t->topo) (void)hipFree(t->topo);
+  for (int i = 0; i < 2; ++i)
+    if (t->stage[i]) (void)hipFree(t->stage[i]);
+  if (t->flags) (void)hipFree(t->flags);
+}
+
+hipError_t tri_launch(cdg2_tri* t, const double* U, const double* U0, double* out, double dt, double ca, double cb,
+                      int stage) {
+  const int nblk = (t->E + TRI_EB - 1) / TRI_EB;
+  if (t->k == 1)
+    hipLaunchKernelGGL((tri_kernel<1>), dim3(nblk), dim3(6 * TRI_EB), 0, t->stream, t->dprm, U, U0, out, dt, ca, cb,
+                       stage, t->flags);
+  else
+    hipLaunchKernelGGL((tri_kernel<2>), dim3(nblk), dim3(6 * TRI_EB), 0, t->stream, t->dprm, U, U0, out, dt, ca, cb,
+                       stage, t->flags);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+int cdg2_tri_create(int order, int n_elements, const double* xy, const int* nbr, const int* nbe,
+                    const cdg2_coeffs* coeffs, double gamma1_in_lo, double gamma1_in_hi, cdg2_tri** out) {
+  if (!out || !xy || !nbr || !nbe || !coeffs) return fail(CDG2_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (order < 1 || order > 2) return fail(CDG2_EINVAL, "triangle order must be 1 or 2");
+  if (n_elements < 1) return fail(CDG2_EINVAL, "n_elements < 1");
+  const int E = n_elements;
+  // topology checks: codes, ranges, reciprocity
+  for (int e = 0; e < E; ++e)
+    for (int j = 0; j < 3; ++j) {
+      const int f = nbr[3 * e + j];
+      if (f >= 0) {
+        const int jj = nbe[3 * e + j];
+        if (f >= E || jj < 0 || jj > 2) return fail(CDG2_EINVAL, "neighbour of element %d edge %d out of range", e, j);
+        if (nbr[3 * f + jj] != e || nbe[3 * f + jj] != j)
+          return fail(CDG2_EINVAL, "neighbour tables not reciprocal at element %d edge %d", e, j);
+      } else if (f != -1 && f != -2) {
+        return fail(CDG2_EINVAL, "boundary code %d at element %d edge %d (allowed: -1, -2)", f, e, j);
+      }
+    }
+  auto* t = new (std::nothrow) cdg2_tri;
+  if (!t) return fail(CDG2_ENOMEM, "out of host memory");
+  t->k = order;
+  t->E = E;
+  t->nb = (order + 1) * (order + 2) / 2;
+  t->ndof = (size_t)6 * E * t->nb;
+  build_tri_tables(order, &t->hp.tb);
+  std::vector<double> geo((size_t)E * (4 + 1 + 3 + 6 + 3));
+  double* jit = geo.data();
+  double* area = jit + 4 * (size_t)E;
+  double* len = area + E;
+  double* nrm = len + 3 * (size_t)E;
+  double* xv = nrm + 6 * (size_t)E;
+  std::vector<int> topo((size_t)E * 9);
+  for (int e = 0; e < E; ++e) {
+    const double* v = xy + 6 * (size_t)e;
+    const double j00 = v[2] - v[0], j10 = v[3] - v[1], j01 = v[4] - v[0], j11 = v[5] - v[1];
+    const double det = j00 * j11 - j01 * j10;
+    if (!(det > 0.0)) {
+      delete t;
+      return fail(CDG2_EINVAL, "element %d is not counter-clockwise (or degenerate)", e);
+    }
+    jit[4 * e + 0] = j11 / det;
+    jit[4 * e + 1] = -j10 / det;
+    jit[4 * e + 2] = -j01 / det;
+    jit[4 * e + 3] = j00 / det;
+    area[e] = 0.5 * det;
+    for (int j = 0; j < 3; ++j) {
+      const int a = j, b = (j + 1) % 3;
+      const double tx = v[2 * b] - v[2 * a], ty = v[2 * b + 1] - v[2 * a + 1];
+      const double L = std::hypot(tx, ty);
+      len[3 * e + j] = L;
+      nrm[6 * e + 2 * j] = ty / L;
+      nrm[6 * e + 2 * j + 1] = -tx / L;
+      xv[3 * e + j] = v[2 * j];
+    }
+  }
+  for (int e = 0; e < E; ++e)
+    for (int j = 0; j < 3; ++j) {
+      const int f = nbr[3 * e + j];
+      topo[3 * e + j] = f;
+      topo[3 * (size_t)E + 3 * e + j] = f >= 0 ? nbe[3 * e + j] : 0;
+      // K^-: the smaller triangle, ties to the lower element index
+      topo[6 * (size_t)E + 3 * e + j] = f >= 0 && (area[e] < area[f] || (area[e] == area[f] && e < f)) ? 1 : 0;
+    }
+  if (hipMalloc((void**)&t->dprm, sizeof(TriParams)) != hipSuccess ||
+      hipMalloc((void**)&t->geo, geo.size() * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&t->topo, topo.size() * sizeof(int)) != hipSuccess ||
+      hipMalloc((void**)&t->stage[0], t->ndof * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&t->stage[1], t->ndof * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&t->flags, 64) != hipSuccess) {
+    tri_free(t);
+    delete t;
+    return fail(CDG2_ENOMEM, "hipMalloc for the triangle mesh failed");
+  }
+  TriGeo& g = t->hp.g;
+  g.E = E;
+  g.jit = t->geo;
+  g.area = t->geo + 4 * (size_t)E;
+  g.len = g.area + E;
+  g.nrm = g.len + 3 * (size_t)E;
+  g.xv = g.nrm + 6 * (size_t)E;
+  g.nbr = t->topo;
+  g.nbe = t->topo + 3 * (size_t)E;
+  g.minus = t->topo + 6 * (size_t)E;
+  g.g1in[0] = gamma1_in_lo;
+  g.g1in[1] = gamma1_in_hi;
+  static_assert(sizeof(cdg2_coeffs) == sizeof(double) * K_NCOEFF, "coefficient order");
+  std::memcpy(t->hp.cf.c, coeffs, sizeof(double) * K_NCOEFF);
+  if (hipMemcpy(t->geo, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(t->topo, topo.data(), topo.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(t->dprm, &t->hp, sizeof(TriParams), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(t->flags, 0, 64) != hipSuccess) {
+    tri_free(t);
+    delete t;
+    return fail(CDG2_EHIP, "triangle mesh upload failed");
+  }
+  *out = t;
+  return CDG2_OK;
+}
+
+int cdg2_tri_destroy(cdg2_tri* t) {
+  if (!t) return CDG2_OK;
+  tri_free(t);
+  delete t;
+  return CDG2_OK;
+}
+
+int cdg2_tri_set_stream(cdg2_tri* t, void* stream) {
+  if (!t) return fail(CDG2_EINVAL, "handle is NULL");
+  t->stream = (hipStream_t)stream;
+  return CDG2_OK;
+}
+
+size_t cdg2_tri_num_dofs(const cdg2_tri* t) { return t ? t->ndof : 0; }
+
+int cdg2_tri_apply_operator(cdg2_tri* t, const double* U, double* F) {
+  if (!t || !U || !F) return fail(CDG2_EINVAL, "NULL argument");
+  if (overlap(U, F, t->ndof * sizeof(double))) return fail(CDG2_EINVAL, "U and F overlap");
+  HIP_TRY(tri_launch(t, U, nullptr, F, 0.0, 0.0, 1.0, 0));
+  return CDG2_OK;
+}
+
+int cdg2_tri_rk_step(cdg2_tri* t, double* U, double dt, int nsteps) {
+  if (!t || !U) return fail(CDG2_EINVAL, "NULL argument");
+  if (nsteps < 0) return fail(CDG2_EINVAL, "nsteps < 0");
+  if (!std::isfinite(dt)) return fail(CDG2_EINVAL, "dt is not finite");
+  const size_t bytes = t->ndof * sizeof(double);
+  if (overlap(U, t->stage[0], bytes) || overlap(U, t->stage[1], bytes))
+    return fail(CDG2_EINVAL, "U overlaps a stage buffer");
+  for (int n = 0; n < nsteps; ++n) {
+    HIP_TRY(tri_launch(t, U, nullptr, t->stage[0], dt, 0.0, 1.0, 1));
+    HIP_TRY(tri_launch(t, t->stage[0], U, t->stage[1], dt, 0.75, 0.25, 2));
+    HIP_TRY(tri_launch(t, t->stage[1], U, U, dt, 1.0 / 3.0, 2.0 / 3.0, 3));
+  }
+  return CDG2_OK;
+}
+
+int cdg2_tri_sync(cdg2_tri* t) {
+  if (!t) return fail(CDG2_EINVAL, "handle is NULL");
+  HIP_TRY(hipStreamSynchronize(t->stream));
+  int f = 0;
+  HIP_TRY(hipMemcpy(&f, t->flags, sizeof f, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemset(t->flags, 0, sizeof(int)));
   if (f & FLAG_NONFINITE) return fail(CDG2_ENONFINITE, "non-finite value written to a state buffer");
   if (f & FLAG_DOMAIN) return fail(CDG2_EDOMAIN, "c + chi^th <= 0 in a chemotactic sensitivity");
   return CDG2_OK;

@@ -104,3 +104,35 @@ def test_null_arguments_rejected():
     assert L.cdg2_batch_create(None, 0, 0, None) == B.CDG2_EINVAL
     assert L.cdg2_destroy(None) == B.CDG2_OK
     assert L.cdg2_num_dofs(None) == 0
+
+
+def test_triangle_mesh_rejected_before_any_device_call():
+    """Invalid triangle meshes and orders fail in the host checks (no GPU needed)."""
+    import numpy as np
+    from paper_1403_1157_amd import inputs
+    xy, nbr, nbe = inputs.kuhn_mesh(3, 2)
+    c = inputs.base_coeffs()
+    L = B.lib()
+    assert L.cdg2_tri_create(1, 1, None, None, None, None, 0.0, 1.0, None) == B.CDG2_EINVAL
+    for order in (0, 3):
+        with pytest.raises(B.CDG2Error) as ei:
+            B.cdg2_tri_create(order, xy, nbr, nbe, c)
+        assert ei.value.code == B.CDG2_EINVAL
+    bad = nbr.copy()
+    bad[0, 1] = (bad[0, 1] + 1) % len(xy)                # not reciprocal
+    with pytest.raises(B.CDG2Error) as ei:
+        B.cdg2_tri_create(1, xy, bad, nbe, c)
+    assert ei.value.code == B.CDG2_EINVAL and "reciprocal" in str(ei.value)
+    code = nbr.copy()
+    code[np.where(nbr == -1)] = -5                        # unknown boundary code
+    with pytest.raises(B.CDG2Error):
+        B.cdg2_tri_create(1, xy, code, nbe, c)
+    cw = xy.copy()
+    cw[0] = cw[0][::-1]                                   # clockwise element
+    with pytest.raises(B.CDG2Error) as ei:
+        B.cdg2_tri_create(1, cw, nbr, nbe, c)
+    assert "counter-clockwise" in str(ei.value)
+    assert L.cdg2_tri_destroy(None) == B.CDG2_OK
+    assert L.cdg2_tri_num_dofs(None) == 0
+    assert L.cdg2_tri_apply_operator(None, None, None) == B.CDG2_EINVAL
+    assert L.cdg2_tri_rk_step(None, None, 0.1, 1) == B.CDG2_EINVAL
