@@ -409,8 +409,8 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
         for (int i = 0; i < Q; ++i) {
           const int m = face_mode<D, Q>(a, i, J);
           const T x = un_src[m];
-          if (m != 0) a0 += T(tb.E[1 - sg][i]) * x;
-          a1 += T(tb.dE[1 - sg][i]) * x;
+          if (m != 0) a0 += T(tb.E[1 - sg][i]) * x;   // the mean apart
+          if (i != 0) a1 += T(tb.dE[1 - sg][i]) * x;  // phi_0' = 0
         }
         mv[J] = a0 * inner;
         md[J] = a1 * (inner * T(g.ih[a]));
