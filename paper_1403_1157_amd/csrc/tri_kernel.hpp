@@ -23,7 +23,7 @@
 
 #include <hip/hip_runtime.h>
 
-#include "op_common.hpp"
+#include "es_kernel.hpp"   // recip4, shared point-pass helpers
 
 namespace cdg2 {
 
@@ -143,7 +143,9 @@ tri_kernel(const TriParams* __restrict__ prm, const double* __restrict__ U, cons
     const double n1 = x[0], n2 = x[NQ], c1 = x[2 * NQ], c3 = x[3 * NQ];
     const double d11 = c1 + c[K_XT11], d13 = c3 + c[K_XT13], d21 = c1 + c[K_XT21], d22 = n1 + c[K_XT22];
     if (e0 + l < E && !(d11 > 0.0 && d13 > 0.0 && d21 > 0.0 && d22 > 0.0)) flag |= FLAG_DOMAIN;
-    const double k11 = c[K_X011] / d11, k13 = c[K_X013] / d13, k21 = c[K_X021] / d21, k22 = c[K_X022] / d22;
+    double r11, r13, r21, r22;
+    recip4(d11, d13, d21, d22, r11, r13, r21, r22);   // one division for the four
+    const double k11 = c[K_X011] * r11, k13 = c[K_X013] * r13, k21 = c[K_X021] * r21, k22 = c[K_X022] * r22;
     double F1[2], F2[2];
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
@@ -261,10 +263,13 @@ tri_kernel(const TriParams* __restrict__ prm, const double* __restrict__ U, cons
         if (!(d11o > 0.0 && d13o > 0.0 && d21o > 0.0 && d22o > 0.0 && d11n > 0.0 && d13n > 0.0 && d21n > 0.0 &&
               d22n > 0.0))
           flag |= FLAG_DOMAIN;
-        const double w1o = c[K_X011] * dc1o / d11o + c[K_X013] * dc3o / d13o;
-        const double w2o = c[K_X021] * dc1o / d21o - c[K_X022] * dn1o / d22o;
-        const double w1n = c[K_X011] * dc1n / d11n + c[K_X013] * dc3n / d13n;
-        const double w2n = c[K_X021] * dc1n / d21n - c[K_X022] * dn1n / d22n;
+        double r11o, r13o, r21o, r22o, r11n, r13n, r21n, r22n;
+        recip4(d11o, d13o, d21o, d22o, r11o, r13o, r21o, r22o);
+        recip4(d11n, d13n, d21n, d22n, r11n, r13n, r21n, r22n);
+        const double w1o = c[K_X011] * dc1o * r11o + c[K_X013] * dc3o * r13o;
+        const double w2o = c[K_X021] * dc1o * r21o - c[K_X022] * dn1o * r22o;
+        const double w1n = c[K_X011] * dc1n * r11n + c[K_X013] * dc3n * r13n;
+        const double w2n = c[K_X021] * dc1n * r21n - c[K_X022] * dn1n * r22n;
         const double lam = fmax(fmax(fabs(w1o), fabs(w2o)), fmax(fabs(w1n), fabs(w2n)));
         x[0] = 0.5 * lam;
         x[NE] = -0.5 * (n1o * w1o + n1n * w1n);
