@@ -635,11 +635,11 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
         dst[m] = v;
       }
     } else {
-      const T* u0 = U0 + s * SE + (size_t)e * NM;
+      const bool combine = ca != T(0);   // U0 is read (and non-null) only then
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
         T v = cb * (u[m] + dt * (R[m] * ivol));
-        if (ca != T(0)) v += ca * u0[m];
+        if (combine) v += ca * U0[s * SE + (size_t)e * NM + m];
         if (!isfinite(v)) flag |= FLAG_NONFINITE;
         dst[m] = v;
       }

@@ -26,10 +26,12 @@
 // modal route: normal contraction with phi_i(end), then the tangential basis.
 //
 // Compared with the modal kernel this removes the modal-to-point transforms of
-// every face and of the volume layers (the FP64 instruction count per thread
-// drops by more than half); the exchange through LDS (volume layers and faces,
-// point items for the nonlinear fluxes) and the staged coalesced loads and
-// stores are the same.
+// every face and of the volume layers (the FP64 instructions per wavefront drop
+// by about a third); the exchange through LDS (volume layers and faces, point
+// items for the nonlinear fluxes) and the staged coalesced loads and stores are
+// the same.  The cell mean is kept apart from the point values (of the
+// fluctuation), so that face jumps of a nearly continuous field keep their
+// digits.
 #pragma once
 
 #include "es_kernel.hpp"

@@ -353,15 +353,13 @@ tri_kernel(const TriParams* __restrict__ prm, const double* __restrict__ U, cons
   // ---- M^{-1}, stage combination, store -------------------------------------------------
   if (live) {
     double* dst = out + s * SE + (size_t)e * NB;
-    const double* u0 = U0 + s * SE + (size_t)e * NB;
     const double ia = 1.0 / area;
+    const bool combine = stage != 0 && ca != 0.0;   // U0 is read (and non-null) only then
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       double v = R[j] * ia;
-      if (stage != 0) {
-        v = cb * (u[j] + dt * v);
-        if (ca != 0.0) v += ca * u0[j];
-      }
+      if (stage != 0) v = cb * (u[j] + dt * v);
+      if (combine) v += ca * U0[s * SE + (size_t)e * NB + j];
       if (!isfinite(v)) flag |= FLAG_NONFINITE;
       dst[j] = v;
     }

@@ -104,6 +104,19 @@ def test_rk_fp32():
     assert_close(Ud, o.rk_step(U, dt, 10), TOL["fp32"], "rk fp32")
 
 
+def test_rk_fp32_3d():
+    """FP32 SSP-RK3 steps on a 3D Q2 grid (the nodal stage kernel in single precision)."""
+    U, cfg = make_case(3, (6, 5, 7), 2, key=(1,), coeffs=strong())
+    U = U.float().double()
+    o = oracle_for(cfg)
+    dt = o.max_dt(U, 0.9)
+    op = gpu_op(cfg, "fp32")
+    Ud = to_dev(U, "fp32")
+    op.rk_step(Ud, dt, 5)
+    op.sync()
+    assert_close(Ud, o.rk_step(U, dt, 5), TOL["fp32"], "rk fp32 3d")
+
+
 @pytest.mark.parametrize("dim,n,p", [(2, (256, 256), 2), (2, (256, 256), 4), (3, (64, 64, 64), 2)])
 def test_full_size_apply_parity(dim, n, p):
     """Full-size workloads (256^2 Q2/Q4, 64^3 Q2) in the benchmark's launch
