@@ -31,13 +31,15 @@ cfl_kernel(const Params* __restrict__ prm, const T* __restrict__ U, unsigned lon
   const int E = g.E;
   const bool live = e0 + el < E;
   const size_t SE = (size_t)E * NM;
+  const int prod = s == S_N1 ? 0 : s == S_N2 ? 1 : s == S_C1 ? 2 : s == S_C3 ? 3 : -1;
   T u[NM];
   {
+    // only n1, n2, c1, c3 enter the velocities and bounds: n3, c2 read nothing
+    const bool need = live && prod >= 0;
     const T* src = U + s * SE + (size_t)(live ? e0 + el : 0) * NM;
 #pragma unroll
-    for (int m = 0; m < NM; ++m) u[m] = live ? src[m] : T(0);
+    for (int m = 0; m < NM; ++m) u[m] = need ? src[m] : T(0);
   }
-  const int prod = s == S_N1 ? 0 : s == S_N2 ? 1 : s == S_C1 ? 2 : s == S_C3 ? 3 : -1;
   const bool grads = s == S_N1 || s == S_C1 || s == S_C3;
   const int gslot = s == S_N1 ? 4 : s == S_C1 ? 4 + D : 4 + 2 * D;
   double lam = 0.0, mn1 = 0.0, mn2 = 0.0;
