@@ -245,6 +245,9 @@ def kuhn_mesh(nx: int, ny: int, jitter: float = 0.0, key: tuple = (7,)):
     periodic images unwrapped), nbr [E, 3] (element across edge j, from vertex j
     to vertex j+1, or -1 on Gamma1, -2 on Gamma2) and nbe [E, 3] (that edge's
     index in the neighbour)."""
+    # with fewer than 3 squares across, two different edges would join the same
+    # pair of (periodic) vertices and the edge matching below would pair them
+    assert nx >= 3 and ny >= 1, "kuhn_mesh needs nx >= 3 and ny >= 1"
     hx, hy = 1.0 / nx, 1.0 / ny
     rng = rng_for(*key)
     dx = rng.uniform(-jitter, jitter, size=(nx, ny + 1)) * hx

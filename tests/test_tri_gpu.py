@@ -29,6 +29,7 @@ def case(nx, ny, k, jitter, key, coeffs, g1=(0.0, 1.0), amp=0.02):
 
 
 @pytest.mark.parametrize("nx,ny,k,jitter,g1", [
+    (3, 1, 2, 0.0, (0.0, 1.0)),         # smallest mesh: 6 triangles, every one on a wall
     (3, 2, 1, 0.0, (0.0, 1.0)),         # 12 elements: one partial workgroup
     (5, 3, 2, 0.25, (0.2, 0.7)),        # 30 elements, jittered, Gamma1,in sub-interval
     (7, 5, 1, 0.3, (0.0, 1.0)),         # 70 elements: several workgroups, ragged tail

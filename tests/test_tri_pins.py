@@ -55,6 +55,18 @@ def test_kuhn_mesh_tables():
     assert (nbr == -1).sum() == 4 and (nbr == -2).sum() == 4
     m = TriMesh(xy, nbr, nbe)
     assert abs(m.area.sum() - 1.0) < 1e-14
+    # every edge: its neighbour's edge joins the same two points (up to the x period)
+    for e in range(E):
+        for j in range(3):
+            f = nbr[e, j]
+            if f >= 0:
+                k = nbe[e, j]
+                a, b = xy[e, j], xy[e, (j + 1) % 3]
+                c, d = xy[f, k], xy[f, (k + 1) % 3]
+                sh = np.round(a[0] - d[0])                 # periodic image offset
+                assert np.allclose(a, d + [sh, 0]) and np.allclose(b, c + [sh, 0])
+    with pytest.raises(AssertionError):
+        inputs.kuhn_mesh(2, 3)
 
 
 @pytest.mark.parametrize("k", [1, 2])
