@@ -70,6 +70,18 @@ def read_traffic(workload: str):
         return None
 
 
+def host_cpu_model() -> str:
+    """Model name of the host CPU (from /proc/cpuinfo, as lscpu reports it)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(dim, n, p, key, dof):
     """Oracle (float64, CPU) on the same workload: one operator application."""
     import torch
@@ -97,7 +109,7 @@ def cpu_baseline(dim, n, p, key, dof):
     finally:
         torch.set_num_threads(threads)
     return {"value": round(dof / sec / 1e9, 6), "unit": "GDOF/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": host_cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"{reps} float64 oracle operator applications on the full workload "
                       f"({dof} DOF), {sec:.2f} s each; GDOF/s = DOF / seconds per application",
             "one_thread": {"value": round(U1.numel() / sec1 / 1e9, 6), "unit": "GDOF/s",

@@ -3,8 +3,9 @@
 The arithmetic runs in libcdg2 (cdg2_batch_*), and so does the schedule search
 (cdg2_batch_autotune times every candidate: cells per work item, persistent
 workgroup count, item order).  This module packs and unpacks torch tensors and
-caches the chosen schedule in a JSON file keyed by the GPU architecture and the
-batch's (grid, order) signature.
+caches the chosen schedule in a JSON file keyed by the GPU architecture, its
+compute-unit count, a hash of the built library (a schedule tuned on other
+kernels is not reused) and the batch's (grid, order) signature.
 """
 from __future__ import annotations
 
@@ -15,6 +16,22 @@ import os
 import torch
 
 from . import cdg2 as B
+
+_LIB_ID = None
+
+
+def library_id() -> str:
+    """Hash of the built libcdg2.so: changes whenever the kernels are rebuilt
+    from other sources."""
+    global _LIB_ID
+    if _LIB_ID is None:
+        h = hashlib.sha256()
+        with open(B.LIB_PATH, "rb") as f:
+            for chunk in iter(lambda: f.read(1 << 20), b""):
+                h.update(chunk)
+        _LIB_ID = h.hexdigest()[:16]
+    return _LIB_ID
+
 
 def default_cache_path() -> str:
     return os.environ.get("CDG2_AUTOTUNE_CACHE",
@@ -79,8 +96,9 @@ class Batch:
         """Schedule of this batch: from the cache if present, else from the
         library's search (cdg2_batch_autotune), then cached."""
         cache_path = cache_path or default_cache_path()
-        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
-        key = f"{arch}:{self.signature()}"
+        prop = torch.cuda.get_device_properties(torch.cuda.current_device())
+        arch = prop.gcnArchName.split(":")[0]
+        key = f"{arch}:cu{prop.multi_processor_count}:lib{library_id()}:{self.signature()}"
         cache = {}
         if os.path.exists(cache_path):
             try:

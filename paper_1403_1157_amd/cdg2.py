@@ -388,6 +388,9 @@ class Operator:
         return lam
 
     def set_coeffs(self, coeffs: dict) -> None:
+        # the parameter upload is queued on the handle's stream: bind the current
+        # one first, so it is ordered after the work already queued there
+        self._stream()
         cdg2_set_coeffs(self.h, coeffs)
 
     def sync(self) -> None:
