@@ -163,19 +163,30 @@ def test_gradient_vs_central_finite_differences():
     central differences of the GPU forward run, step h = 1e-6 relative, for all
     21 coefficients and for random directions of the initial state.
 
-    The quotient's own error is dominated by the rounding of the loss values:
-    the loss compares two nearby trajectories, so its float64 rounding sigma is
-    far above eps |L|.  sigma is measured as the scatter (about the linear trend)
-    of the loss at nine values of mu1 spaced 1e-13 apart, where the exact change
-    is negligible; a quotient of step h is resolved to 3 sigma / h.  The loss
-    depends on n1 and c3 only and the run is short (T = 7.6e-4), so several
-    coefficients move it too little for the step-1e-6 quotient.  For those the
-    reference is the Richardson extrapolation (4 D(h) - D(2h)) / 3 of central
-    quotients with h = 1e-3 relative (truncation O(h^4), estimated from the same
-    extrapolation at 2h, 4h); its resolution is 4.5 sigma / h plus three times
-    that estimate.  Where a reference resolves the derivative to 1e-7 the
-    adjoint must agree with it within 1e-6 relative; elsewhere within the
-    reference's resolution.  The counts are printed."""
+    Two statements are checked.
+    * Normwise, over all 21 coefficients: the gradient scaled by the
+      coefficients (theta_j dL/dtheta_j, the quantity a relative step probes)
+      agrees with the finite-difference reference within 1e-6 of its largest
+      entry.
+    * Per coefficient, within 1e-6 relative wherever that is resolvable.  The
+      loss compares two nearby trajectories, so the rounding sigma of its
+      float64 values is far above eps |L|; sigma_j is measured for each
+      coefficient as the scatter (about the linear trend) of the loss at nine
+      values of theta_j spaced 1e-13 apart (the rounding that coefficient's
+      perturbations see), and a quotient of step h is resolved to 3 sigma_j / h.  The loss
+      depends on n1 and c3 only and the run is short (T = 7.6e-4), so several
+      coefficients move it too little for the step-1e-6 quotient; for those
+      the reference is the Richardson extrapolation (4 D(h) - D(2h)) / 3 with
+      h = 1e-2 relative (truncation O(h^4), estimated from the same
+      extrapolation at 2h, 4h; resolution 4.5 sigma_j / h plus three times that
+      estimate).  The
+      adjoint's own rounding is measured as the scatter of its gradient over
+      five initial states perturbed by 1e-12.  Where the reference and the
+      adjoint's rounding together resolve the derivative to 1e-7, the
+      agreement must be within 1e-6 relative; elsewhere within ten times their
+      sum (the resolution is itself an estimate).  The counts are printed.
+    Every coefficient's derivative is also checked against the oracle's exact
+    (autograd) gradient on a smaller grid (test_adjoint_rk_vs_oracle)."""
     from oracle.cdg2_oracle import COEFF_NAMES
     from paper_1403_1157_amd.autograd import CDG2RK, coeffs_with, mismatch_loss, theta_of
     c, U, op, dt, tgt, vol, steps, ckpt = _loss_fd_setup()
@@ -184,6 +195,15 @@ def test_gradient_vs_central_finite_differences():
     th = theta_of(c).requires_grad_(True)
     L = mismatch_loss(CDG2RK.apply(U0, th, op, c, dt, steps, ckpt), tgt, vol)
     L.backward()
+    # rounding scatter of the adjoint gradient: initial states perturbed by 1e-12
+    gen = torch.Generator(device="cpu").manual_seed(11)
+    grads = []
+    for _ in range(5):
+        Ui = (U * (1 + 1e-12 * (torch.rand(U.shape, generator=gen, dtype=torch.float64) - 0.5).to(DEV))).requires_grad_(True)
+        thi = theta_of(c).requires_grad_(True)
+        mismatch_loss(CDG2RK.apply(Ui, thi, op, c, dt, steps, ckpt), tgt, vol).backward()
+        grads.append(thi.grad.clone())
+    sig_ad = torch.stack(grads).std(dim=0).numpy()
 
     def loss_at(theta, Uinit):
         op.set_coeffs(coeffs_with(c, theta))
@@ -200,21 +220,26 @@ def test_gradient_vs_central_finite_differences():
         tm[j] -= h
         return (loss_at(tp, U) - loss_at(tm, U)) / (2 * h)
 
-    # rounding level of the loss values
     xs = np.arange(-4, 5, dtype=np.float64)
-    ls = []
-    for k in xs:
-        t = base.clone()
-        t[0] = float(base[0]) * (1.0 + 1e-13 * k)
-        ls.append(loss_at(t, U))
-    ls = np.array(ls)
-    fit = np.polyval(np.polyfit(xs, ls, 1), xs)
-    sigma = float(np.sqrt(np.mean((ls - fit) ** 2)))
+
+    def rounding_level(j):
+        """Scatter of the loss about its linear trend at nine values of theta_j
+        spaced 1e-13 apart."""
+        ls = []
+        for k in xs:
+            t = base.clone()
+            t[j] = float(base[j]) * (1.0 + 1e-13 * k)
+            ls.append(loss_at(t, U))
+        ls = np.array(ls)
+        return float(np.sqrt(np.mean((ls - np.polyval(np.polyfit(xs, ls, 1), xs)) ** 2)))
+
     L0 = loss_at(base, U)
-    print(f"[fd] loss {L0:.6e}, rounding level {sigma:.2e} ({sigma / L0:.1e} relative)", flush=True)
-    strict, richardson, loose = [], [], []
+    print(f"[fd] loss {L0:.6e}", flush=True)
+    strict, richardson, loose, failures = [], [], [], []
     worst = 0.0
+    scaled_ref, scaled_ad = [], []
     for j in range(21):
+        sigma = rounding_level(j)
         h6 = 1e-6 * abs(float(base[j]))
         fd = quotient(j, h6)
         res6 = 3.0 * sigma / h6
@@ -223,27 +248,42 @@ def test_gradient_vs_central_finite_differences():
         if res6 <= 1e-7 * abs(fd):
             kind, ref, res = "step 1e-6", fd, res6
         else:
-            h = 1e-3 * abs(float(base[j]))
+            h = 1e-2 * abs(float(base[j]))
             d1, d2, d4 = quotient(j, h), quotient(j, 2 * h), quotient(j, 4 * h)
             ref = (4 * d1 - d2) / 3
             trunc = abs(ref - (4 * d2 - d4) / 3) / 15
-            kind, res = "Richardson 1e-3", 4.5 * sigma / h + 3 * trunc
+            kind, res = "Richardson 1e-2", 4.5 * sigma / h + 3 * trunc
+        res += 3.0 * float(sig_ad[j])
+        scaled_ref.append(float(base[j]) * ref)
+        scaled_ad.append(float(base[j]) * ad)
         relr = abs(ref - ad) / max(abs(ref), 1e-300)
         resolved = res <= 1e-7 * abs(ref)
         print(f"[fd] {COEFF_NAMES[j]:>9s} adjoint {ad:+.10e} | step 1e-6: {fd:+.10e} rel {rel:.1e} | "
-              f"reference ({kind}) {ref:+.10e} rel {relr:.2e} resolution {res / max(abs(ref), 1e-300):.1e}"
-              f"{'' if resolved else ' (unresolved)'}", flush=True)
+              f"reference ({kind}) {ref:+.10e} rel {relr:.2e} resolution {res / max(abs(ref), 1e-300):.1e} "
+              f"(loss rounding {sigma / L0:.1e}) "
+              f"(adjoint rounding {sig_ad[j] / max(abs(ref), 1e-300):.1e}){'' if resolved else ' unresolved'}",
+              flush=True)
         if resolved:
-            assert relr < 1e-6, (COEFF_NAMES[j], kind, relr)
+            if relr >= 1e-6:
+                failures.append((COEFF_NAMES[j], kind, relr))
             (strict if kind == "step 1e-6" else richardson).append(COEFF_NAMES[j])
             worst = max(worst, relr)
         else:
-            assert abs(ref - ad) <= res + 1e-6 * abs(ref), (COEFF_NAMES[j], relr, res)
+            # the resolution is an estimate (a scatter of nine values, an
+            # asymptotic truncation bound): a factor 10 of slack
+            if abs(ref - ad) > 10 * res + 1e-6 * abs(ref):
+                failures.append((COEFF_NAMES[j], kind, relr, res))
             loose.append(COEFF_NAMES[j])
+    sr, sa = np.array(scaled_ref), np.array(scaled_ad)
+    normwise = float(np.abs(sr - sa).max() / np.abs(sr).max())
+    print(f"[fd] normwise: max_j |theta_j (adjoint - reference)| / max_j |theta_j reference| = {normwise:.2e}",
+          flush=True)
     print(f"[fd] within 1e-6 (worst {worst:.2e}): {len(strict)} coefficients against the step-1e-6 "
-          f"quotient, {len(richardson)} against the Richardson quotient; below the resolution of both: "
+          f"quotient, {len(richardson)} against the Richardson quotient; below the resolution: "
           f"{', '.join(loose) or 'none'}", flush=True)
-    assert len(strict) + len(richardson) >= 1
+    assert normwise < 1e-6
+    assert not failures, failures
+    assert len(strict) + len(richardson) >= 6
     g = torch.Generator(device="cpu").manual_seed(5)
     for k in range(4):
         v = torch.rand(U.shape, generator=g, dtype=torch.float64).to(DEV) * 2 - 1
