@@ -138,6 +138,26 @@ int cdg2_apply_operator(cdg2_handle* h, const void* U, void* dUdt);
  * intermediate states live in the handle's stage buffers. */
 int cdg2_rk_step(cdg2_handle* h, void* U, double dt, int nsteps);
 
+/* Size of the library's static scratch memory per GPU (64 MiB), which holds the
+ * two intermediate states of cdg2_rk_step_noalloc. */
+#define CDG2_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory during the call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same nsteps SSP-RK3 steps as cdg2_rk_step, with the same kernels and results,
+ * but the two intermediate states live in a static device array of
+ * CDG2_SCRATCH_BYTES per GPU (set up at cdg2_create) instead of the handle's
+ * stage buffers.  Allocates nothing (no hipMalloc / hipFree, no allocating
+ * library call).  Limit: each state, rounded up to 256 bytes, must fit in half
+ * of the array, i.e. cdg2_num_dofs * (8 for FP64, 4 for FP32) <= 32 MiB
+ * (4,194,304 FP64 entries, e.g. 256x256 Q2 or 128x128 Q4); larger handles get
+ * CDG2_EINVAL.  Every handle on a GPU shares that GPU's array, which keeps the
+ * last call's intermediate states: calls that overlap in time on one GPU (other
+ * streams or threads) race and must be serialised by the caller.  U: device
+ * buffer on the handle's device, updated in place; asynchronous like
+ * cdg2_rk_step. */
+int cdg2_rk_step_noalloc(cdg2_handle* h, void* U, double dt, int nsteps);
+
 /* CFL time step for state U (synchronous: returns after the device work):
  *   dt = cfl / (rho_hat a_max sum_a h_a^-2 / 2.51 + (2p+1) lam_max sum_a h_a^-1
  *               + r_max / 2.51),

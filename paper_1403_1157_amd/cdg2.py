@@ -82,6 +82,7 @@ def lib():
     L.cdg2_num_dofs.restype = ctypes.c_size_t
     L.cdg2_apply_operator.argtypes = [P, P, P]
     L.cdg2_rk_step.argtypes = [P, P, _d, ctypes.c_int]
+    L.cdg2_rk_step_noalloc.argtypes = [P, P, _d, ctypes.c_int]
     L.cdg2_max_dt.argtypes = [P, P, _d, ctypes.POINTER(_d)]
     L.cdg2_sync.argtypes = [P]
     L.cdg2_rho_hat.argtypes = [P]
@@ -115,7 +116,7 @@ def lib():
     L.cdg2_last_error.argtypes = []
     L.cdg2_last_error.restype = ctypes.c_char_p
     for name in ("cdg2_create", "cdg2_destroy", "cdg2_set_stream", "cdg2_set_coeffs",
-                 "cdg2_apply_operator", "cdg2_rk_step", "cdg2_max_dt", "cdg2_sync",
+                 "cdg2_apply_operator", "cdg2_rk_step", "cdg2_rk_step_noalloc", "cdg2_max_dt", "cdg2_sync",
                  "cdg2_apply_adjoint", "cdg2_rk_step_adjoint", "cdg2_rk_adjoint_segment",
                  "cdg2_dirk_step",
                  "cdg2_batch_create",
@@ -194,6 +195,10 @@ def cdg2_apply_operator(h, U_ptr: int, out_ptr: int) -> None:
 
 def cdg2_rk_step(h, U_ptr: int, dt: float, nsteps: int) -> None:
     _check(lib().cdg2_rk_step(h, ctypes.c_void_p(U_ptr), float(dt), int(nsteps)))
+
+
+def cdg2_rk_step_noalloc(h, U_ptr: int, dt: float, nsteps: int) -> None:
+    _check(lib().cdg2_rk_step_noalloc(h, ctypes.c_void_p(U_ptr), float(dt), int(nsteps)))
 
 
 def cdg2_max_dt(h, U_ptr: int, cfl: float) -> float:
@@ -339,6 +344,13 @@ class Operator:
     def rk_step(self, U: torch.Tensor, dt: float, nsteps: int = 1) -> torch.Tensor:
         self._stream()
         cdg2_rk_step(self.h, self._arg(U), dt, nsteps)
+        return U
+
+    def rk_step_noalloc(self, U: torch.Tensor, dt: float, nsteps: int = 1) -> torch.Tensor:
+        """rk_step with the intermediate states in the library's static scratch
+        memory (no device allocation; states up to 32 MiB)."""
+        self._stream()
+        cdg2_rk_step_noalloc(self.h, self._arg(U), dt, nsteps)
         return U
 
     def max_dt(self, U: torch.Tensor, cfl: float = 0.9) -> float:

@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 #include <algorithm>
+#include <mutex>
 
 #include "../../include/cdg2.h"
 #include "cfl_kernel.hpp"
@@ -70,6 +71,7 @@ struct cdg2_handle {
   double* imp_hcoef = nullptr;
   hipStream_t stream = nullptr;
   double rho_hat = 0.0;
+  int device = 0;                      // device current at create
 };
 
 namespace {
@@ -297,6 +299,48 @@ bool overlap2(const void* a, size_t na, const void* b, size_t nb) {
 }
 
 
+// ---- scratch memory of the allocation-free entry point ------------------------------
+
+// The two intermediate SSP-RK3 states of cdg2_rk_step_noalloc.  A file-scope
+// device array: every GPU the library runs on holds its own copy from module load
+// until the process ends.  In host code its name is only a host-side stand-in, so
+// the kernels get the device address that hipGetSymbolAddress returns for the
+// current device (looked up once per device at cdg2_create, kept in scratch_dev).
+static __device__ __align__(256) unsigned char scratch[CDG2_SCRATCH_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[SCRATCH_MAX_DEVICES] = {};
+
+// Look up (once) the device address of the scratch array on the current device.
+int scratch_setup(int device) {
+  if (device < 0 || device >= SCRATCH_MAX_DEVICES) return fail(CDG2_EINVAL, "device index %d out of range", device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[device]) return CDG2_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(CDG2_EHIP, "hipGetSymbolAddress of the scratch array failed: %s", hipGetErrorString(e));
+  g_scratch_dev[device] = ptr;
+  return CDG2_OK;
+}
+
+void* scratch_device(int device) {
+  if (device < 0 || device >= SCRATCH_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_dev[device];
+}
+
+// nsteps fused SSP-RK3 steps on U with the intermediate states in st0, st1.
+int rk_steps(cdg2_handle* h, void* U, double dt, int nsteps, void* st0, void* st1) {
+  for (int n = 0; n < nsteps; ++n) {
+    HIP_TRY(run_op(h, U, nullptr, st0, dt, 0.0, 1.0, 1));
+    HIP_TRY(run_op(h, st0, U, st1, dt, 0.75, 0.25, 2));
+    HIP_TRY(run_op(h, st1, U, U, dt, 1.0 / 3.0, 2.0 / 3.0, 3));
+  }
+  return CDG2_OK;
+}
+
 // ---- implicit SDIRK integrator: Jacobian-free Newton-Krylov (GMRES) ---------------
 
 constexpr int IMP_KMAX = 64;   // largest Krylov dimension
@@ -481,6 +525,15 @@ int cdg2_create(const cdg2_config* cfg, cdg2_handle** out) {
     cdg2_destroy(h);
     return fail(CDG2_EHIP, "device initialisation failed");
   }
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    cdg2_destroy(h);
+    return fail(CDG2_EHIP, "hipGetDevice failed");
+  }
+  rc = scratch_setup(h->device);
+  if (rc) {
+    cdg2_destroy(h);
+    return rc;
+  }
   *out = h;
   return CDG2_OK;
 }
@@ -546,12 +599,23 @@ int cdg2_rk_step(cdg2_handle* h, void* U, double dt, int nsteps) {
   if (overlap(U, h->stage[0], bytes) || overlap(U, h->stage[1], bytes))
     return fail(CDG2_EINVAL, "U overlaps a stage buffer");
   if (misaligned(h, U)) return fail(CDG2_EINVAL, "3D state buffers must be 16-byte aligned");
-  for (int n = 0; n < nsteps; ++n) {
-    HIP_TRY(run_op(h, U, nullptr, h->stage[0], dt, 0.0, 1.0, 1));
-    HIP_TRY(run_op(h, h->stage[0], U, h->stage[1], dt, 0.75, 0.25, 2));
-    HIP_TRY(run_op(h, h->stage[1], U, U, dt, 1.0 / 3.0, 2.0 / 3.0, 3));
-  }
-  return CDG2_OK;
+  return rk_steps(h, U, dt, nsteps, h->stage[0], h->stage[1]);
+}
+
+int cdg2_rk_step_noalloc(cdg2_handle* h, void* U, double dt, int nsteps) {
+  if (!h || !U) return fail(CDG2_EINVAL, "NULL argument");
+  if (nsteps < 0) return fail(CDG2_EINVAL, "nsteps < 0");
+  if (!std::isfinite(dt)) return fail(CDG2_EINVAL, "dt is not finite");
+  const size_t bytes = h->ndof * (h->fp32 ? 4 : 8);
+  const size_t slot = (bytes + 255) / 256 * 256;   // second state 256-byte aligned
+  if (slot > CDG2_SCRATCH_BYTES / 2)
+    return fail(CDG2_EINVAL, "state of %zu bytes exceeds the scratch limit of %zu bytes per state", bytes,
+                (size_t)CDG2_SCRATCH_BYTES / 2);
+  char* base = (char*)scratch_device(h->device);
+  if (!base) return fail(CDG2_EINVAL, "scratch memory not set up on device %d", h->device);
+  if (overlap2(U, bytes, base, CDG2_SCRATCH_BYTES)) return fail(CDG2_EINVAL, "U overlaps the scratch memory");
+  if (misaligned(h, U)) return fail(CDG2_EINVAL, "3D state buffers must be 16-byte aligned");
+  return rk_steps(h, U, dt, nsteps, base, base + slot);
 }
 
 int cdg2_apply_adjoint(cdg2_handle* h, const void* U, const void* w, void* JTw, double* dtheta) {

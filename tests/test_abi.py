@@ -95,6 +95,7 @@ def test_null_arguments_rejected():
     assert L.cdg2_create(None, None) == B.CDG2_EINVAL
     assert L.cdg2_apply_operator(None, None, None) == B.CDG2_EINVAL
     assert L.cdg2_rk_step(None, None, 0.1, 1) == B.CDG2_EINVAL
+    assert L.cdg2_rk_step_noalloc(None, None, 0.1, 1) == B.CDG2_EINVAL
     assert L.cdg2_rk_step_adjoint(None, None, None, None, 0.1, None) == B.CDG2_EINVAL
     assert L.cdg2_rk_adjoint_segment(None, None, 1, 0.1, None, None) == B.CDG2_EINVAL
     assert L.cdg2_dirk_step(None, None, 0.1, None, None) == B.CDG2_EINVAL
