@@ -296,18 +296,21 @@ int cdg2_batch_rk(cdg2_batch* b, void* U_packed, const size_t* offsets, const do
 /* Wait for the batch's stream; report non-finite / domain conditions. */
 int cdg2_batch_sync(cdg2_batch* b);
 
-/* ---- unstructured triangle meshes (P_k, k = 1, 2; FP64) -------------------------
+/* ---- unstructured triangle meshes (P_k, k = 1, 2, 3; FP64) ----------------------
  *
  * The same six-species operator on a conforming triangle mesh (Section 3.1 on
  * simplices, the element type of the paper's own runs): full P_k per triangle
  * with an orthonormal basis (phi_0 = 1, so mode 0 is the element mean and
  * M_K = |K| I; the reference basis is the Gram-Schmidt orthonormalisation, for
  * the mean over the reference triangle (0,0), (1,0), (0,1), of the monomials
- * 1, xi, eta, xi^2, xi eta, eta^2 in that order), collapsed Gauss rules of k + 1
+ * xi^a eta^b by total degree, then by the power of eta: 1, xi, eta, xi^2, xi eta,
+ * eta^2, xi^3, ...), collapsed Gauss rules of k + 1
  * points per direction on the triangle and k + 1 Gauss points per edge, the LLF
  * and CDG2 fluxes (lifting on K^-: the smaller triangle of an edge, ties to the
  * lower element index; chi_e = 3/2) and the inflow fluxes of eqs. (7)-(9) on the
- * edges coded Gamma1 / Gamma2.  State layout: U[6][E][(k+1)(k+2)/2] doubles,
+ * edges coded Gamma1 / Gamma2.  order: k = 1, 2 or 3 (else CDG2_EINVAL; Table 1
+ * of Section 4 uses the linear, quadratic and cubic spaces).  State layout:
+ * U[6][E][(k+1)(k+2)/2] doubles,
  * species n1, n2, n3, c1, c2, c3.
  *
  * Mesh (HOST arrays, copied at create):

@@ -7,11 +7,13 @@ path.
 What it computes (Section 3.1 on simplices, the element type the paper uses):
 the residual <phi_j, L_h(U)> of the six-species model of Section 2 with
 
-  * V_h = P_k on each triangle K (full polynomial space, k = 1, 2), basis
+  * V_h = P_k on each triangle K (full polynomial space, k = 1, 2, 3), basis
     phi_j = phi^_j o F_K^{-1} with phi^_j orthonormal on the reference
     triangle T^ = {xi, eta >= 0, xi + eta <= 1} for the mean (1/|T^|) int_T^,
-    built by Gram-Schmidt from the monomials 1, xi, eta, xi^2, xi eta, eta^2 in
-    that order; so phi_0 = 1 (mode 0 is the cell mean) and M_K = |K| I;
+    built by Gram-Schmidt from the monomials xi^a eta^b ordered by total degree,
+    then by the power of eta (1, xi, eta, xi^2, xi eta, eta^2, xi^3, ...),
+    evaluated about the centroid; so
+    phi_0 = 1 (mode 0 is the cell mean) and M_K = |K| I;
   * volume integrals with the collapsed (Duffy) Gauss rule of k + 1 points per
     direction: (xi, eta) = (u, v (1 - u)), weight w_u w_v (1 - u), exact for
     total degree 2k (the mass matrix);
@@ -87,12 +89,19 @@ class TriBasis:
         self.C = C                                     # phi_j = sum_m C[j, m] mono_m
         self.nb = nb
 
+    # The monomials are taken about the centroid (1/3, 1/3): each one differs from
+    # the plain xi^a eta^b by monomials earlier in the order, so every prefix spans
+    # the same space and Gram-Schmidt gives the same basis; evaluated about the
+    # centroid the expansion cancels far less (plain monomials leave the P3 basis
+    # orthonormal only to ~1e-12).
+    CENTRE = 1.0 / 3.0
+
     def _mono(self, pts):
-        xi, eta = pts[:, 0], pts[:, 1]
+        xi, eta = pts[:, 0] - self.CENTRE, pts[:, 1] - self.CENTRE
         return np.stack([xi ** a * eta ** b for a, b in self.pw], axis=1)
 
     def _mono_grad(self, pts):
-        xi, eta = pts[:, 0], pts[:, 1]
+        xi, eta = pts[:, 0] - self.CENTRE, pts[:, 1] - self.CENTRE
         gx = [a * xi ** max(a - 1, 0) * eta ** b if a > 0 else 0.0 * xi for a, b in self.pw]
         gy = [b * xi ** a * eta ** max(b - 1, 0) if b > 0 else 0.0 * xi for a, b in self.pw]
         return np.stack(gx, axis=1), np.stack(gy, axis=1)

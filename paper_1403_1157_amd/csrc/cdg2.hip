@@ -1306,7 +1306,8 @@ struct cdg2_tri {
 namespace {
 
 // Orthonormal basis of P_k on the reference triangle for the mean, by modified
-// Gram-Schmidt of the monomials xi^a eta^b (total degree, then power of eta),
+// Gram-Schmidt of the monomials xi^a eta^b (total degree, then power of eta;
+// taken about the centroid),
 // with a collapsed Gauss rule exact for the products; then its values and
 // gradients at the volume and edge points of the operator's rules.
 void build_tri_tables(int k, TriTables* t) {
@@ -1318,7 +1319,11 @@ void build_tri_tables(int k, TriTables* t) {
       pw[nb][1] = b;
       ++nb;
     }
-  auto mono = [&](double x, double y, double* v, double* gx, double* gy) {
+  // monomials about the centroid (1/3, 1/3): every prefix of the order spans the
+  // same space as the plain monomials (the same Gram-Schmidt basis), with far less
+  // cancellation when the basis is evaluated (P3 stays orthonormal to ~1e-14)
+  auto mono = [&](double x0, double y0, double* v, double* gx, double* gy) {
+    const double x = x0 - 1.0 / 3.0, y = y0 - 1.0 / 3.0;
     for (int m = 0; m < nb; ++m) {
       const int a = pw[m][0], b = pw[m][1];
       v[m] = std::pow(x, a) * std::pow(y, b);
@@ -1426,8 +1431,11 @@ hipError_t tri_launch(cdg2_tri* t, const double* U, const double* U0, double* ou
   if (t->k == 1)
     hipLaunchKernelGGL((tri_kernel<1>), dim3(nblk), dim3(6 * TRI_EB), 0, t->stream, t->dprm, U, U0, out, dt, ca, cb,
                        stage, t->flags);
-  else
+  else if (t->k == 2)
     hipLaunchKernelGGL((tri_kernel<2>), dim3(nblk), dim3(6 * TRI_EB), 0, t->stream, t->dprm, U, U0, out, dt, ca, cb,
+                       stage, t->flags);
+  else
+    hipLaunchKernelGGL((tri_kernel<3>), dim3(nblk), dim3(6 * TRI_EB), 0, t->stream, t->dprm, U, U0, out, dt, ca, cb,
                        stage, t->flags);
   return hipGetLastError();
 }
@@ -1440,7 +1448,7 @@ int cdg2_tri_create(int order, int n_elements, const double* xy, const int* nbr,
                     const cdg2_coeffs* coeffs, double gamma1_in_lo, double gamma1_in_hi, cdg2_tri** out) {
   if (!out || !xy || !nbr || !nbe || !coeffs) return fail(CDG2_EINVAL, "NULL argument");
   *out = nullptr;
-  if (order < 1 || order > 2) return fail(CDG2_EINVAL, "triangle order must be 1 or 2");
+  if (order < 1 || order > 3) return fail(CDG2_EINVAL, "triangle order must be 1, 2 or 3");
   if (n_elements < 1) return fail(CDG2_EINVAL, "n_elements < 1");
   const int E = n_elements;
   // topology checks: codes, ranges, reciprocity

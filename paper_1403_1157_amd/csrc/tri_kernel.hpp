@@ -1,4 +1,4 @@
-// CDG2 operator on unstructured triangle meshes (P_k, k = 1, 2), FP64, one thread
+// CDG2 operator on unstructured triangle meshes (P_k, k = 1, 2, 3), FP64, one thread
 // per (element, species).
 //
 // The discrete operator (Section 3.1 on simplices): basis phi_j = phi^_j o F_K^-1
@@ -27,9 +27,9 @@
 
 namespace cdg2 {
 
-constexpr int TRI_MAXB = 6;    // P_2
-constexpr int TRI_MAXQ = 9;    // (k + 1)^2 volume points
-constexpr int TRI_MAXE = 3;    // k + 1 edge points
+constexpr int TRI_MAXB = 10;   // P_3
+constexpr int TRI_MAXQ = 16;   // (k + 1)^2 volume points
+constexpr int TRI_MAXE = 4;    // k + 1 edge points
 constexpr int TRI_EB = 32;     // elements per workgroup (192 threads)
 
 // Reference tables (host-built).
@@ -66,7 +66,7 @@ struct TriParams {
 template <int K>
 struct TriSz {
   static constexpr int NB = (K + 1) * (K + 2) / 2, NQ = (K + 1) * (K + 1), NE = K + 1;
-  static constexpr int NVQ = 15;   // volume slots: 0 n1 1 n2 2 c1 3 c3 | 4,5 grad n1 | 6,7 grad c1 | 8,9 grad c3 | 13 n3 14 c2
+  static constexpr int NVQ = 12;   // volume slots: 0 n1 1 n2 2 c1 3 c3 | 4,5 grad n1 | 6,7 grad c1 | 8,9 grad c3 | 10 n3 11 c2
   static constexpr int NFQ = 14;   // edge slots as in the Cartesian kernel
 };
 
@@ -79,10 +79,12 @@ struct TriSmem {
   double etab[3 * S::NE * S::NB * 3];   // edge tables: [edge][point][mode][value, d/dxi, d/deta]
 };
 
-// At least 3 waves per SIMD: P2 then fits 152 VGPRs (1.4x faster than the 2 waves
-// its free allocation of 172 VGPRs allowed).
+// At least 3 waves per SIMD for P1, P2: P2 then fits 152 VGPRs (1.4x faster than
+// the 2 waves its free allocation of 172 VGPRs allowed).  P3 at 2 waves: its
+// 52 KB of LDS holds a CU to three workgroups anyway, and under the 3-wave
+// bound it spilled.
 template <int K>
-__global__ void __launch_bounds__(6 * TRI_EB, 3)
+__global__ void __launch_bounds__(6 * TRI_EB, K == 3 ? 2 : 3)
 tri_kernel(const TriParams* __restrict__ prm, const double* __restrict__ U, const double* U0, double* out,
            double dt, double ca, double cb, int stage, int* __restrict__ flags) {
   using S = TriSz<K>;
@@ -122,7 +124,7 @@ tri_kernel(const TriParams* __restrict__ prm, const double* __restrict__ U, cons
 
   // ---- volume ---------------------------------------------------------------------
   double* V = sm.buf;   // [EB][NVQ][NQ]
-  const int vslot = s == S_N1 ? 0 : s == S_N2 ? 1 : s == S_C1 ? 2 : s == S_C3 ? 3 : s == S_N3 ? 13 : 14;
+  const int vslot = s == S_N1 ? 0 : s == S_N2 ? 1 : s == S_C1 ? 2 : s == S_C3 ? 3 : s == S_N3 ? 10 : 11;
   const int gslot = s == S_N1 ? 4 : s == S_C1 ? 6 : s == S_C3 ? 8 : -1;
   double gq[NQ][2];
   {
@@ -175,7 +177,7 @@ tri_kernel(const TriParams* __restrict__ prm, const double* __restrict__ U, cons
     // linear reactions: n1 -d1 n1; n2 -d2 n2; n3 (d1 - gamma) n1 + d2 n2; c1 f1 n3 (+ alpha
     // term); c2 -k c2; c3 k c2
     const double kown = s == S_N1 ? -c[K_D1] : s == S_N2 ? -c[K_D2] : s == S_C2 ? -c[K_K] : 0.0;
-    const int r0 = s == S_N3 ? 0 : s == S_C1 ? 13 : s == S_C3 ? 14 : 0;
+    const int r0 = s == S_N3 ? 0 : s == S_C1 ? 10 : s == S_C3 ? 11 : 0;
     const double k0 = s == S_N3 ? c[K_D1] - c[K_GAM] : s == S_C1 ? c[K_F1] : s == S_C3 ? c[K_K] : 0.0;
     const double k1 = s == S_N3 ? c[K_D2] : 0.0;
     const int fs = s == S_N2 ? 6 : 4;

@@ -115,7 +115,7 @@ def test_triangle_mesh_rejected_before_any_device_call():
     c = inputs.base_coeffs()
     L = B.lib()
     assert L.cdg2_tri_create(1, 1, None, None, None, None, 0.0, 1.0, None) == B.CDG2_EINVAL
-    for order in (0, 3):
+    for order in (0, 4):
         with pytest.raises(B.CDG2Error) as ei:
             B.cdg2_tri_create(order, xy, nbr, nbe, c)
         assert ei.value.code == B.CDG2_EINVAL

@@ -34,6 +34,8 @@ def case(nx, ny, k, jitter, key, coeffs, g1=(0.0, 1.0), amp=0.02):
     (5, 3, 2, 0.25, (0.2, 0.7)),        # 30 elements, jittered, Gamma1,in sub-interval
     (7, 5, 1, 0.3, (0.0, 1.0)),         # 70 elements: several workgroups, ragged tail
     (8, 6, 2, 0.2, (0.3, 0.6)),
+    (3, 1, 3, 0.0, (0.0, 1.0)),         # P3 on the smallest mesh
+    (7, 5, 3, 0.3, (0.2, 0.7)),         # P3: several workgroups, ragged tail, Gamma1,in
 ])
 def test_tri_apply_parity(nx, ny, k, jitter, g1):
     o, op, U = case(nx, ny, k, jitter, (nx, ny, k), strong(), g1)
@@ -43,7 +45,7 @@ def test_tri_apply_parity(nx, ny, k, jitter, g1):
     assert_close(f, o.apply(U), TOL["fp64"], f"tri apply {nx}x{ny} k{k}")
 
 
-@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("k", [1, 2, 3])
 def test_tri_rk_steps_parity(k):
     o, op, U = case(6, 5, k, 0.2, (11, k), strong(), (0.25, 0.75))
     dt = 2e-4
@@ -54,7 +56,7 @@ def test_tri_rk_steps_parity(k):
     assert_close(Ud, o.rk_step(U, dt, 10), TOL["fp64"], f"tri rk k{k}")
 
 
-@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("k", [1, 2, 3])
 def test_tri_large_mesh_apply_parity(k):
     """64 x 64 squares (8192 triangles), jittered: every output against the oracle."""
     o, op, U = case(64, 64, k, 0.2, (12, k), strong())

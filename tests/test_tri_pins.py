@@ -26,7 +26,7 @@ def diffusion(a=0.05):
     return c
 
 
-@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("k", [1, 2, 3])
 def test_basis_orthonormal_and_mean_mode(k):
     b = TriBasis(k)
     p, w = duffy_rule(k + 4)
@@ -69,7 +69,7 @@ def test_kuhn_mesh_tables():
         inputs.kuhn_mesh(2, 3)
 
 
-@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("k", [1, 2, 3])
 def test_constant_state_has_no_flux(k):
     """A constant state: every diffusive, chemotactic and penalty term vanishes
     (zero gradients, zero jumps); with the inflow switched off what is left is
@@ -90,7 +90,7 @@ def test_constant_state_has_no_flux(k):
     assert f[:, :, 1:].abs().max() < 1e-13
 
 
-@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("k", [1, 2, 3])
 def test_diffusion_form_symmetric_negative_semidefinite(k):
     """The CDG2 diffusion form is symmetric and coercive: <phi_i, L_h phi_j>
     (one species, pure diffusion, zero-flux walls) is a symmetric negative
@@ -110,7 +110,7 @@ def test_diffusion_form_symmetric_negative_semidefinite(k):
     assert (ev > -1e-10 * scale).sum() == 1          # only the constants
 
 
-@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("k", [1, 2, 3])
 def test_conservation_of_means_under_zero_flux(k):
     m = mesh(4, 3, 0.2)
     o = TriOracle(m, k, diffusion(0.3))
