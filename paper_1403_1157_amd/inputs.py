@@ -296,3 +296,81 @@ def tri_modes(E: int, k: int, key: tuple = (8,), amp: float = 0.02) -> np.ndarra
     U = rng.uniform(-amp, amp, size=(6, E, nb))
     U[:, :, 0] = rng.uniform(0.3, 0.7, size=(6, E))
     return U
+
+
+def kuhn_tet_mesh(nx: int, ny: int, nz: int, jitter: float = 0.0, key: tuple = (17,)):
+    """Tetrahedral mesh of [0,1]^3: each of nx x ny x nz cubes split into the six
+    tetrahedra of its Kuhn (Freudenthal) subdivision along the main diagonal,
+    periodic in x and y, walls z = 0 (Gamma1) and z = 1 (Gamma2).  Optional seeded
+    jitter moves every vertex by up to `jitter` cell widths (z only off the walls),
+    which makes the tetrahedra unequal.
+
+    Returns xyz [E, 4, 3] (vertex coordinates per element, positively oriented,
+    periodic images unwrapped), vid [E, 4] (periodic vertex ids), nbr [E, 4]
+    (element across the face opposite local vertex f, or -1 on Gamma1, -2 on
+    Gamma2) and nbe [E, 4] (that face's index in the neighbour)."""
+    # with fewer than 3 cubes across a periodic axis two different faces would
+    # join the same (periodic) vertices and the face matching would pair them
+    assert nx >= 3 and ny >= 3 and nz >= 1, "kuhn_tet_mesh needs nx, ny >= 3"
+    h = (1.0 / nx, 1.0 / ny, 1.0 / nz)
+    rng = rng_for(*key)
+    d = rng.uniform(-jitter, jitter, size=(3, nx, ny, nz + 1)) * np.array(h)[:, None, None, None]
+    d[2, :, :, 0] = 0.0
+    d[2, :, :, nz] = 0.0
+
+    def vert(i, j, l):
+        ii, jj = i % nx, j % ny
+        p = (i * h[0] + d[0, ii, jj, l], j * h[1] + d[1, ii, jj, l], l * h[2] + d[2, ii, jj, l])
+        return p, ii + nx * (jj + ny * l)
+
+    paths = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+    xyz, vid = [], []
+    for l in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                for path in paths:
+                    c = [0, 0, 0]
+                    pts, ids = [], []
+                    for step in (None,) + path:
+                        if step is not None:
+                            c[step] += 1
+                        p, v = vert(i + c[0], j + c[1], l + c[2])
+                        pts.append(p)
+                        ids.append(v)
+                    P = np.array(pts)
+                    if np.linalg.det(np.stack([P[1] - P[0], P[2] - P[0], P[3] - P[0]], axis=1)) < 0:
+                        pts[1], pts[2] = pts[2], pts[1]
+                        ids[1], ids[2] = ids[2], ids[1]
+                    xyz.append(pts)
+                    vid.append(ids)
+    xyz = np.array(xyz, dtype=np.float64)
+    vid = np.array(vid, dtype=np.int32)
+    E = len(vid)
+    faces = ((1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2))
+    nbr = np.full((E, 4), -9, dtype=np.int32)
+    nbe = np.full((E, 4), -1, dtype=np.int32)
+    owner = {}
+    for e in range(E):
+        for f, vs in enumerate(faces):
+            k2 = tuple(sorted(int(vid[e, v]) for v in vs))
+            if k2 in owner:
+                g, gf = owner.pop(k2)
+                nbr[e, f], nbe[e, f] = g, gf
+                nbr[g, gf], nbe[g, gf] = e, f
+            else:
+                owner[k2] = (e, f)
+    layer = nx * ny
+    for k2, (e, f) in owner.items():
+        nbr[e, f] = -1 if max(k2) < layer else -2
+    assert (nbr != -9).all()
+    return xyz, vid, nbr, nbe
+
+
+def tet_modes(E: int, k: int, key: tuple = (18,), amp: float = 0.02) -> np.ndarray:
+    """Random modal coefficients U[6, E, (k+1)(k+2)(k+3)/6] of a positive field on
+    a tetrahedral mesh: element means in [0.3, 0.7], the other modes within +-amp."""
+    rng = rng_for(*key)
+    nb = (k + 1) * (k + 2) * (k + 3) // 6
+    U = rng.uniform(-amp, amp, size=(6, E, nb))
+    U[:, :, 0] = rng.uniform(0.3, 0.7, size=(6, E))
+    return U
