@@ -341,6 +341,54 @@ int cdg2_tri_rk_step(cdg2_tri* t, double* U, double dt, int nsteps);
  * CDG2_EDOMAIN) raised by the launches since the last call. */
 int cdg2_tri_sync(cdg2_tri* t);
 
+/* ---- unstructured tetrahedral meshes (P_k, k = 1, 2, 3; FP64) -------------------
+ *
+ * The same six-species operator on a conforming tetrahedral mesh (Section 3.1 on
+ * tetrahedra, the element of the paper's 3D runs, whose Table 2 uses cubic
+ * elements): full P_k per tetrahedron with an orthonormal basis (phi_0 = 1,
+ * M_K = |K| I; Gram-Schmidt, for the mean over the reference tetrahedron (0,0,0),
+ * (1,0,0), (0,1,0), (0,0,1), of the monomials xi^a eta^b zeta^c ordered by total
+ * degree, then by the power of zeta, then of eta, taken about the centroid);
+ * volume integrals with the collapsed Gauss rule of (k+2)(k+1)^2 points, face
+ * integrals with a fully symmetric triangle rule of degree 2k (3, 6, 12 points;
+ * its orbit parameters solve the moment equations) so that both elements of a
+ * face use the same points; LLF and CDG2 fluxes (lifting on K^-: the smaller
+ * tetrahedron of a face, ties to the lower element index; chi_e = 2) and the
+ * inflow fluxes of eqs. (7)-(9) on the faces coded Gamma1 / Gamma2.  State
+ * layout: U[6][E][(k+1)(k+2)(k+3)/6] doubles, species n1, n2, n3, c1, c2, c3.
+ *
+ * Mesh (HOST arrays, copied at create):
+ *   xyz  [E][4][3]  vertex coordinates of each element, positively oriented
+ *                   (det[v1-v0, v2-v0, v3-v0] > 0, else CDG2_EINVAL); periodic
+ *                   images are given unwrapped, so each element is a proper
+ *                   tetrahedron;
+ *   vid  [E][4]     mesh vertex ids (the same id for the same vertex in every
+ *                   element and periodic image): they fix how the two elements
+ *                   of a face see its points;
+ *   nbr  [E][4]     element across local face f (the face opposite local vertex
+ *                   f), or -1 (Gamma1) / -2 (Gamma2);
+ *   nbe  [E][4]     that face's index in the neighbour (ignored on boundaries).
+ * The tables must be reciprocal and a face and its neighbour's must carry the same
+ * three vertex ids, else CDG2_EINVAL.  Gamma_{1,in} is the set of Gamma1 points
+ * with x in [gamma1_in_lo, gamma1_in_hi]. */
+typedef struct cdg2_tet cdg2_tet;
+int cdg2_tet_create(int order, int n_elements, const double* xyz, const int* vid, const int* nbr, const int* nbe,
+                    const cdg2_coeffs* coeffs, double gamma1_in_lo, double gamma1_in_hi, cdg2_tet** out);
+int cdg2_tet_destroy(cdg2_tet* t);
+/* Stream of all later launches (NULL: the default stream). */
+int cdg2_tet_set_stream(cdg2_tet* t, void* stream);
+/* 6 E (k+1)(k+2)(k+3)/6. */
+size_t cdg2_tet_num_dofs(const cdg2_tet* t);
+/* F = M^-1 L_h(U) (DEVICE arrays of cdg2_tet_num_dofs doubles, not overlapping).
+ * Asynchronous; see cdg2_tet_sync. */
+int cdg2_tet_apply_operator(cdg2_tet* t, const double* U, double* F);
+/* nsteps SSP-RK3 steps of size dt on U in place (DEVICE), the stage combination
+ * fused into the operator kernel. */
+int cdg2_tet_rk_step(cdg2_tet* t, double* U, double dt, int nsteps);
+/* Wait for the stream; report non-finite / domain conditions raised since the
+ * last call. */
+int cdg2_tet_sync(cdg2_tet* t);
+
 /* Thread-local message of the last error. */
 const char* cdg2_last_error(void);
 

@@ -113,6 +113,15 @@ def lib():
     L.cdg2_tri_apply_operator.argtypes = [P, P, P]
     L.cdg2_tri_rk_step.argtypes = [P, P, _d, ctypes.c_int]
     L.cdg2_tri_sync.argtypes = [P]
+    L.cdg2_tet_create.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, ctypes.POINTER(cdg2_coeffs), _d, _d,
+                                  ctypes.POINTER(P)]
+    L.cdg2_tet_destroy.argtypes = [P]
+    L.cdg2_tet_set_stream.argtypes = [P, P]
+    L.cdg2_tet_num_dofs.argtypes = [P]
+    L.cdg2_tet_num_dofs.restype = ctypes.c_size_t
+    L.cdg2_tet_apply_operator.argtypes = [P, P, P]
+    L.cdg2_tet_rk_step.argtypes = [P, P, _d, ctypes.c_int]
+    L.cdg2_tet_sync.argtypes = [P]
     L.cdg2_last_error.argtypes = []
     L.cdg2_last_error.restype = ctypes.c_char_p
     for name in ("cdg2_create", "cdg2_destroy", "cdg2_set_stream", "cdg2_set_coeffs",
@@ -123,7 +132,8 @@ def lib():
                  "cdg2_batch_destroy", "cdg2_batch_set_stream", "cdg2_batch_set_schedule",
                  "cdg2_batch_rk", "cdg2_batch_sync", "cdg2_batch_autotune", "cdg2_batch_set_graph",
                  "cdg2_tri_create", "cdg2_tri_destroy", "cdg2_tri_set_stream", "cdg2_tri_apply_operator",
-                 "cdg2_tri_rk_step", "cdg2_tri_sync"):
+                 "cdg2_tri_rk_step", "cdg2_tri_sync", "cdg2_tet_create", "cdg2_tet_destroy",
+                 "cdg2_tet_set_stream", "cdg2_tet_apply_operator", "cdg2_tet_rk_step", "cdg2_tet_sync"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -510,6 +520,97 @@ class TriOperator:
     def close(self):
         if self.h is not None:
             cdg2_tri_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- unstructured tetrahedral meshes ---------------------------------------------------
+
+def cdg2_tet_create(order: int, xyz, vid, nbr, nbe, coeffs: dict, gamma1_in=(0.0, 1.0)) -> int:
+    import numpy as np
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    vid = np.ascontiguousarray(vid, dtype=np.int32)
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    nbe = np.ascontiguousarray(nbe, dtype=np.int32)
+    E = xyz.shape[0]
+    if xyz.shape != (E, 4, 3) or vid.shape != (E, 4) or nbr.shape != (E, 4) or nbe.shape != (E, 4):
+        raise ValueError("xyz must be [E, 4, 3], vid, nbr and nbe [E, 4]")
+    h = ctypes.c_void_p()
+    c = make_coeffs(coeffs)
+    _check(lib().cdg2_tet_create(int(order), E, xyz.ctypes.data, vid.ctypes.data, nbr.ctypes.data, nbe.ctypes.data,
+                                 ctypes.byref(c), float(gamma1_in[0]), float(gamma1_in[1]), ctypes.byref(h)))
+    return h.value
+
+
+def cdg2_tet_destroy(h) -> None:
+    _check(lib().cdg2_tet_destroy(h))
+
+
+def cdg2_tet_set_stream(h, stream) -> None:
+    _check(lib().cdg2_tet_set_stream(h, stream))
+
+
+def cdg2_tet_num_dofs(h) -> int:
+    return int(lib().cdg2_tet_num_dofs(h))
+
+
+def cdg2_tet_apply_operator(h, U: int, F: int) -> None:
+    _check(lib().cdg2_tet_apply_operator(h, U, F))
+
+
+def cdg2_tet_rk_step(h, U: int, dt: float, nsteps: int) -> None:
+    _check(lib().cdg2_tet_rk_step(h, U, float(dt), int(nsteps)))
+
+
+def cdg2_tet_sync(h) -> None:
+    _check(lib().cdg2_tet_sync(h))
+
+
+class TetOperator:
+    """The operator on a tetrahedral mesh (xyz [E, 4, 3], vid, nbr, nbe [E, 4]; see
+    cdg2_tet_create in include/cdg2.h); states are contiguous CUDA float64 tensors
+    (6, E, (k+1)(k+2)(k+3)/6)."""
+
+    def __init__(self, order, xyz, vid, nbr, nbe, coeffs, gamma1_in=(0.0, 1.0)):
+        self.order = int(order)
+        self.E = int(len(xyz))
+        self.nb = (self.order + 1) * (self.order + 2) * (self.order + 3) // 6
+        self.shape = (6, self.E, self.nb)
+        self.h = cdg2_tet_create(order, xyz, vid, nbr, nbe, coeffs, gamma1_in)
+        assert cdg2_tet_num_dofs(self.h) == 6 * self.E * self.nb
+
+    def _arg(self, t: torch.Tensor) -> int:
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == self.shape):
+            raise ValueError(f"expected a contiguous CUDA float64 tensor of {self.shape}")
+        return t.data_ptr()
+
+    def _stream(self):
+        cdg2_tet_set_stream(self.h, torch.cuda.current_stream().cuda_stream)
+
+    def apply(self, U: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty_like(U)
+        self._stream()
+        cdg2_tet_apply_operator(self.h, self._arg(U), self._arg(out))
+        return out
+
+    def rk_step(self, U: torch.Tensor, dt: float, nsteps: int = 1) -> torch.Tensor:
+        self._stream()
+        cdg2_tet_rk_step(self.h, self._arg(U), dt, nsteps)
+        return U
+
+    def sync(self) -> None:
+        self._stream()
+        cdg2_tet_sync(self.h)
+
+    def close(self):
+        if self.h is not None:
+            cdg2_tet_destroy(self.h)
             self.h = None
 
     def __del__(self):

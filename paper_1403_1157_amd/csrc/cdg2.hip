@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 #include <algorithm>
+#include <array>
 #include <mutex>
 
 #include "../../include/cdg2.h"
@@ -18,6 +19,7 @@
 #include "es_kernel.hpp"
 #include "nodal_kernel.hpp"
 #include "tri_kernel.hpp"
+#include "tet_kernel.hpp"
 #include "vec_kernel.hpp"
 #include "tables.cpp"
 
@@ -1594,3 +1596,7 @@ int cdg2_tri_sync(cdg2_tri* t) {
 }
 
 }  // extern "C"
+
+// ---- unstructured tetrahedral meshes (P_k) ----------------------------------------
+
+#include "tet_api.hpp"

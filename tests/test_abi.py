@@ -137,3 +137,37 @@ def test_triangle_mesh_rejected_before_any_device_call():
     assert L.cdg2_tri_num_dofs(None) == 0
     assert L.cdg2_tri_apply_operator(None, None, None) == B.CDG2_EINVAL
     assert L.cdg2_tri_rk_step(None, None, 0.1, 1) == B.CDG2_EINVAL
+
+
+def test_tetrahedral_mesh_rejected_before_any_device_call():
+    """Invalid tetrahedral meshes and orders fail in the host checks."""
+    import numpy as np
+    from paper_1403_1157_amd import inputs
+    xyz, vid, nbr, nbe = inputs.kuhn_tet_mesh(3, 3, 1)
+    c = inputs.base_coeffs()
+    L = B.lib()
+    assert L.cdg2_tet_create(1, 1, None, None, None, None, None, 0.0, 1.0, None) == B.CDG2_EINVAL
+    for order in (0, 4):
+        with pytest.raises(B.CDG2Error) as ei:
+            B.cdg2_tet_create(order, xyz, vid, nbr, nbe, c)
+        assert ei.value.code == B.CDG2_EINVAL
+    bad = nbr.copy()
+    bad[0, 0] = (bad[0, 0] + 1) % len(xyz)                 # not reciprocal
+    with pytest.raises(B.CDG2Error) as ei:
+        B.cdg2_tet_create(1, xyz, vid, bad, nbe, c)
+    assert "reciprocal" in str(ei.value)
+    vbad = vid.copy()
+    e, f = np.argwhere(nbr >= 0)[0]
+    vbad[e, (f + 1) % 4] = vid.max() + 7                 # a face vertex its neighbour lacks
+    with pytest.raises(B.CDG2Error) as ei:
+        B.cdg2_tet_create(1, xyz, vbad, nbr, nbe, c)
+    assert ei.value.code == B.CDG2_EINVAL
+    neg = xyz.copy()
+    neg[0, [1, 2]] = neg[0, [2, 1]]                      # negatively oriented element
+    with pytest.raises(B.CDG2Error) as ei:
+        B.cdg2_tet_create(1, neg, vid, nbr, nbe, c)
+    assert "oriented" in str(ei.value)
+    assert L.cdg2_tet_destroy(None) == B.CDG2_OK
+    assert L.cdg2_tet_num_dofs(None) == 0
+    assert L.cdg2_tet_apply_operator(None, None, None) == B.CDG2_EINVAL
+    assert L.cdg2_tet_rk_step(None, None, 0.1, 1) == B.CDG2_EINVAL
