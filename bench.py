@@ -15,8 +15,9 @@ float64), inputs resident in HBM.  Prints ONE JSON line.
 Extras in the same line (skipped with --no-extras): the 256^2 Q2/Q4 workloads
 (graph-replayed applies, 100-step runs), the batched 256-instance run against
 the plain entry point, the adjoint (forward + gradient against forward), the
-implicit SDIRK step against the explicit steps over the same interval, and the
-comparison diffusion fluxes on the exact heat solution.
+implicit SDIRK step against the explicit steps over the same interval, the
+comparison diffusion fluxes on the exact heat solution, and the unstructured
+triangle (P1-P3) and tetrahedral (P2, P3; the size of the paper's 3D run) meshes.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 (default K = 50: the 50-step run of the 64^3 workload)
@@ -279,7 +280,7 @@ def bench_fluxes(n=(128, 128), p=2, a=0.05, T=0.02):
     P = torch.from_numpy(inputs.heat_modes(n, p, T, a)).cuda()
     vol = 1.0 / (n[0] * n[1])
     out = {}
-    for flux in ("cdg2", "br2", "ip", "bo"):
+    for flux in ("cdg2", "br2", "ip", "bo", "cdg"):
         op = Operator(2, n, p, c, diff_flux=flux)
         dt = op.max_dt(U0, 0.9)
         nst = int(math.ceil(T / dt))
@@ -297,7 +298,7 @@ def bench_fluxes(n=(128, 128), p=2, a=0.05, T=0.02):
 
 def bench_triangles(n=256, steps=100, reps=200):
     """Unstructured P_k triangles: an n x n Kuhn mesh of [0,1]^2 with jittered
-    vertices (2 n^2 triangles), P1 and P2; operator applications and an SSP-RK3
+    vertices (2 n^2 triangles), P1, P2 and P3; operator applications and an SSP-RK3
     run.  Algorithmic bytes as for the Cartesian grids (16 B/DOF per apply,
     64 B/DOF per step, state only)."""
     import torch
@@ -307,7 +308,7 @@ def bench_triangles(n=256, steps=100, reps=200):
 
     xy, nbr, nbe = inputs.kuhn_mesh(n, n, 0.2, (14,))
     out = {}
-    for k in (1, 2):
+    for k in (1, 2, 3):
         op = TriOperator(k, xy, nbr, nbe, inputs.base_coeffs())
         U0 = torch.from_numpy(inputs.tri_modes(len(xy), k, key=(15, k), amp=0.005)).cuda()
         dof = U0.numel()
@@ -326,6 +327,40 @@ def bench_triangles(n=256, steps=100, reps=200):
                         "gdof_s": round(3 * dof / us_step / 1e3, 3)}
     return {"workload": f"{n}x{n} Kuhn mesh, jittered ({2 * n * n} triangles), {reps} applies and a "
                         f"{steps}-step SSP-RK3 run", **out}
+
+
+def bench_tetrahedra(n=(26, 26, 28), steps=20, reps=50):
+    """Unstructured P_k tetrahedra at the size of the paper's 3D strong-scaling run
+    (cubic elements, 113,549 tetrahedra): a jittered Kuhn mesh of 26 x 26 x 28
+    cubes, 113,568 tetrahedra; P3 (13,628,160 DOF) and P2; operator applications
+    and an SSP-RK3 run.  Algorithmic bytes as for the other grids (state only)."""
+    import torch
+
+    from paper_1403_1157_amd import inputs
+    from paper_1403_1157_amd.cdg2 import TetOperator
+
+    xyz, vid, nbr, nbe = inputs.kuhn_tet_mesh(*n, 0.2, (24,))
+    out = {}
+    for k in (3, 2):
+        op = TetOperator(k, xyz, vid, nbr, nbe, inputs.base_coeffs())
+        U0 = torch.from_numpy(inputs.tet_modes(len(xyz), k, key=(25, k), amp=0.005)).cuda()
+        dof = U0.numel()
+        F = torch.empty_like(U0)
+        op.apply(U0, F)
+        op.sync()
+        us_apply = 1e3 * time_ms(lambda: op.apply(U0, F), reps)
+        U = U0.clone()
+        op.rk_step(U, 1e-8, 2)
+        op.sync()
+        U = U0.clone()
+        us_step = 1e3 * time_ms(lambda: op.rk_step(U, 1e-8, steps)) / steps
+        op.sync()
+        out[f"p{k}"] = {"dof": dof, "us_per_apply": round(us_apply, 2),
+                        "apply_frac": round(16 * dof / us_apply / 1e3 / HBM_PEAK_GBS, 4),
+                        "us_per_step": round(us_step, 2), "step_frac": round(64 * dof / us_step / 1e3 / HBM_PEAK_GBS, 4),
+                        "gdof_s": round(3 * dof / us_step / 1e3, 3)}
+    return {"workload": f"{'x'.join(map(str, n))} Kuhn cubes, jittered ({len(xyz)} tetrahedra), {reps} applies and "
+                        f"a {steps}-step SSP-RK3 run", **out}
 
 
 def bench_2d(reps=1000, steps=100):
@@ -503,6 +538,7 @@ def main():
         line["implicit"] = bench_implicit()
         line["fluxes"] = bench_fluxes()
         line["triangles"] = bench_triangles()
+        line["tetrahedra"] = bench_tetrahedra()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(dim, n, p, key, dof)
     print(json.dumps(line), flush=True)

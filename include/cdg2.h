@@ -69,11 +69,16 @@ enum { CDG2_LLF_ALL = 0, CDG2_LLF_CELLS = 1 };
  *   CDG2: 2 chi_e (A r_e([[U]]))|_{K^-}, chi_e = N/2 (N = 2 dim faces per cell);
  *   BR2:  eta {A r_e([[U]])} (average of the liftings on both neighbours);
  *   IP:   eta A (p+1)^2 / h [[U]] (symmetric interior penalty);
- *   BO:   Baumann-Oden: no stabilisation, symmetry term with the opposite sign.
+ *   BO:   Baumann-Oden: no stabilisation, symmetry term with the opposite sign;
+ *   CDG:  compact DG (the paper names it without details; read as Peraire and
+ *         Persson's method with the switch selecting K^-): the flux and the
+ *         symmetry term are one-sided, A (grad U^- + r~([[U]])).n^- with r~ the
+ *         lifting of the whole jump onto K^- only (no average).
  * On uniform Cartesian cells the lifting has the same trace from both sides
  * (-(p+1)^2 / (2h) [[U]]), so BR2 with eta = N and IP with eta = dim coincide
- * with CDG2.  flux_eta = 0 selects eta = 2 dim for BR2 and IP. */
-enum { CDG2_FLUX_CDG2 = 0, CDG2_FLUX_BR2 = 1, CDG2_FLUX_IP = 2, CDG2_FLUX_BO = 3 };
+ * with CDG2, and CDG is the one-sided form with penalty (p+1)^2 a / h.
+ * flux_eta = 0 selects eta = 2 dim for BR2 and IP. */
+enum { CDG2_FLUX_CDG2 = 0, CDG2_FLUX_BR2 = 1, CDG2_FLUX_IP = 2, CDG2_FLUX_BO = 3, CDG2_FLUX_CDG = 4 };
 
 /* Coefficients of Section 2 (the paper gives symbols only).  The first 21 are
  * the differentiable coefficients in this order: mu1..3, nu1..3 (motilities),
@@ -222,8 +227,8 @@ int cdg2_dirk_step(cdg2_handle* h, void* U, double dt, const cdg2_implicit_opts*
  * waits for the device.  Non-smooth points: d|x|/dx = sign(x) (0 at 0), the max
  * of the LLF speed takes the first maximiser, the inflow Heaviside has
  * derivative 0.  Parameter sums are reduced in a fixed order (deterministic).
- * Symmetric diffusion fluxes only (CDG2, BR2, IP): CDG2_EINVAL for Baumann-Oden,
- * as for the other adjoint entry points. */
+ * Central symmetric diffusion fluxes only (CDG2, BR2, IP): CDG2_EINVAL for
+ * Baumann-Oden and CDG, as for the other adjoint entry points. */
 int cdg2_apply_adjoint(cdg2_handle* h, const void* U, const void* w, void* JTw, double* dtheta);
 
 /* Discrete adjoint of one SSP-RK3 step of size dt started from U_n: given

@@ -43,7 +43,13 @@ Readings where the paper is silent or garbled:
   * the LLF dissipation speed is the spectral radius of d(F.n)/dU, i.e.
     max(|w1.n|, |w2.n|) over both sides, applied to all six rows ("all") or only
     to the two cell rows ("cells");
-  * F^:[[phi]] is read as (F^ n^-)(phi^- - phi^+).
+  * F^:[[phi]] is read as (F^ n^-)(phi^- - phi^+);
+  * the comparison fluxes of Section 4 (named there without their constants):
+    BR2 eta {A r_e}, interior penalty eta A (p+1)^2/h [[U]], Baumann-Oden (no
+    stabilisation, symmetry term of the opposite sign), and CDG read as the
+    compact DG of Peraire and Persson with its switch on K^-: one-sided flux
+    A (grad U^- + r~).n^- with the lifting r~ of the whole jump onto K^- and the
+    symmetry term on K^- only.
 """
 from __future__ import annotations
 
@@ -78,7 +84,7 @@ class Config:
     gamma1_in: tuple = (0.0, 1.0)
     llf_mode: str = "all"        # "all" | "cells"
     coeffs: dict = field(default_factory=dict)
-    diff_flux: str = "cdg2"      # "cdg2" | "br2" | "ip" | "bo" (diffusion flux, Section 3.1)
+    diff_flux: str = "cdg2"      # "cdg2" | "br2" | "ip" | "bo" | "cdg" (diffusion flux, Section 3.1)
     flux_eta: float = 0.0        # penalty of br2 / ip; 0: default (br2: N = 2d, ip: 2d)
 
     def resolved_wall(self) -> int:
@@ -206,7 +212,7 @@ class Oracle:
         self.nm = (p + 1) ** d
         self.wall = cfg.resolved_wall()
         self.chi_e = float(d)             # N/2 with N = 2d faces per cell
-        assert cfg.diff_flux in ("cdg2", "br2", "ip", "bo")
+        assert cfg.diff_flux in ("cdg2", "br2", "ip", "bo", "cdg")
         self.flux_eta = float(cfg.flux_eta) if cfg.flux_eta > 0 else float(2 * d)
         self.vol = math.prod(self.h)
         x1, w1 = gauss_legendre01(self.q)
@@ -362,12 +368,12 @@ class Oracle:
         else:
             diss = torch.cat([0.5 * lam[None] * jump[:2], torch.zeros_like(jump[2:])])
             Fhat = Fn + diss
-        # consistency average {A grad U}.n^-
+        # consistency average {A grad U}.n^- (CDG: one-sided, the K^- value)
         ab = a.reshape(6, *([1] * (jump.dim() - 1)))
-        avg = 0.5 * ab * (dnm + dnp)
+        flux = self.cfg.diff_flux
+        avg = ab * dnm if flux == "cdg" else 0.5 * ab * (dnm + dnp)
         # diffusion stabilisation (the comparison fluxes of Section 4 share the
         # consistency term; they differ in the stabilisation and the symmetry term)
-        flux = self.cfg.diff_flux
         if flux == "cdg2":
             # CDG2: lifting on K^- (general route: mass solve on K^-)
             Ahat = 2.0 * self.chi_e * ab * self.lift_trace(jump, ax)
@@ -378,6 +384,11 @@ class Oracle:
         elif flux == "ip":
             # interior penalty: eta a (p+1)^2 / h [[U]]
             Ahat = -self.flux_eta * ab * (self.p + 1) ** 2 / self.h[ax] * jump
+        elif flux == "cdg":
+            # compact DG with the switch on K^-: the lifting of the whole jump onto
+            # K^- only, int_{K^-} r~ . tau = -int_e [[V]] . tau (twice the half-jump
+            # lifting of lift_trace), and no average
+            Ahat = 2.0 * ab * self.lift_trace(jump, ax)
         else:
             # Baumann-Oden: no stabilisation, symmetry term with the opposite sign
             Ahat = torch.zeros_like(jump)
@@ -385,12 +396,16 @@ class Oracle:
         sym = 0.5 * ab * jump                                        # multiplies dn phi (both sides)
         if flux == "bo":
             sym = -sym
+        sym_m, sym_p = sym, sym
+        if flux == "cdg":
+            # one-sided symmetry term: on K^- only, with the whole jump
+            sym_m, sym_p = 2.0 * sym, torch.zeros_like(sym)
         wf = F["wf"]
         # test functions on K- (trace at xi_ax = 1) and on K+ (xi_ax = 0)
         Rm = torch.einsum("t,s...t,tm->s...m", wf, gflux, F["PhiHi"]) \
-            + torch.einsum("t,s...t,tm->s...m", wf, sym, F["dPhiHi"][..., ax])
+            + torch.einsum("t,s...t,tm->s...m", wf, sym_m, F["dPhiHi"][..., ax])
         Rp = -torch.einsum("t,s...t,tm->s...m", wf, gflux, F["PhiLo"]) \
-            + torch.einsum("t,s...t,tm->s...m", wf, sym, F["dPhiLo"][..., ax])
+            + torch.einsum("t,s...t,tm->s...m", wf, sym_p, F["dPhiLo"][..., ax])
         if not periodic:
             # the face after the last cell along the wall axis does not exist
             n = self.n[ax]

@@ -18,8 +18,9 @@ CDG2_OK, CDG2_EINVAL, CDG2_ENOMEM, CDG2_EHIP, CDG2_ENONFINITE, CDG2_EDOMAIN = 0,
 CDG2_ENOCONV = -6
 CDG2_FP64, CDG2_FP32 = 0, 1
 CDG2_LLF_ALL, CDG2_LLF_CELLS = 0, 1
-CDG2_FLUX_CDG2, CDG2_FLUX_BR2, CDG2_FLUX_IP, CDG2_FLUX_BO = 0, 1, 2, 3
-FLUXES = {"cdg2": CDG2_FLUX_CDG2, "br2": CDG2_FLUX_BR2, "ip": CDG2_FLUX_IP, "bo": CDG2_FLUX_BO}
+CDG2_FLUX_CDG2, CDG2_FLUX_BR2, CDG2_FLUX_IP, CDG2_FLUX_BO, CDG2_FLUX_CDG = 0, 1, 2, 3, 4
+FLUXES = {"cdg2": CDG2_FLUX_CDG2, "br2": CDG2_FLUX_BR2, "ip": CDG2_FLUX_IP, "bo": CDG2_FLUX_BO,
+          "cdg": CDG2_FLUX_CDG}
 
 COEFF_NAMES = [
     "mu1", "mu2", "mu3", "nu1", "nu2", "nu3",

@@ -99,7 +99,7 @@ int validate(const cdg2_config* c) {
     return fail(CDG2_EINVAL, "precision must be CDG2_FP64 or CDG2_FP32");
   if (c->wall_axis < -1 || c->wall_axis >= c->dim) return fail(CDG2_EINVAL, "wall_axis out of range");
   if (c->llf_mode != CDG2_LLF_ALL && c->llf_mode != CDG2_LLF_CELLS) return fail(CDG2_EINVAL, "bad llf_mode");
-  if (c->diff_flux < CDG2_FLUX_CDG2 || c->diff_flux > CDG2_FLUX_BO) return fail(CDG2_EINVAL, "bad diff_flux");
+  if (c->diff_flux < CDG2_FLUX_CDG2 || c->diff_flux > CDG2_FLUX_CDG) return fail(CDG2_EINVAL, "bad diff_flux");
   if (!(c->flux_eta >= 0) || !std::isfinite(c->flux_eta)) return fail(CDG2_EINVAL, "flux_eta must be finite and >= 0");
   if (!(c->gamma1_in[0] <= c->gamma1_in[1])) return fail(CDG2_EINVAL, "gamma1_in must be an interval");
   const double* v = &c->coeffs.mu[0];
@@ -134,10 +134,16 @@ void build_geo(const cdg2_config& c, Geo* g) {
   // Cartesian cells) and the sign of its symmetry term
   const double nf = 2.0 * c.dim, eta = c.flux_eta > 0 ? c.flux_eta : 2.0 * c.dim;
   g->sym = 1.0;
+  g->wm = g->wp = 0.5;
   switch (c.diff_flux) {
     case CDG2_FLUX_BR2: g->pen_c = 0.5 * eta; break;       // eta {r_e}: trace (p+1)^2/(2h) per side
     case CDG2_FLUX_IP: g->pen_c = eta; break;
     case CDG2_FLUX_BO: g->pen_c = 0.0; g->sym = -1.0; break;
+    case CDG2_FLUX_CDG:   // one-sided on K^-: gradient plus the lifting of the whole jump there
+      g->pen_c = 1.0;
+      g->wm = 1.0;
+      g->wp = 0.0;
+      break;
     default: g->pen_c = 0.5 * nf; break;                    // CDG2: 2 chi_e r_e|K-, chi_e = N/2
   }
   g->tz = c.dim == 3 ? 8 : 0;   // slabs of 8 z-planes (processing order of the 3D kernel)
@@ -253,7 +259,8 @@ hipError_t run_adj(cdg2_handle* h, const void* U, const void* W, void* out, doub
 int ensure_adjoint(cdg2_handle* h) {
   // the adjoint applies the diffusion form to the adjoint state unchanged, which
   // needs the form to be symmetric
-  if (h->geo.sym < 0) return fail(CDG2_EINVAL, "the adjoint needs a symmetric diffusion flux (CDG2, BR2 or IP)");
+  if (h->geo.sym < 0 || h->geo.wm != 0.5)
+    return fail(CDG2_EINVAL, "the adjoint needs a central symmetric diffusion flux (CDG2, BR2 or IP)");
   if (h->part) return CDG2_OK;
   size_t bytes = h->ndof * (h->fp32 ? 4 : 8);
   int nb = (h->geo.E + 31) / 32;
@@ -509,7 +516,7 @@ int cdg2_create(const cdg2_config* cfg, cdg2_handle** out) {
   size_t nm = 1;
   for (int a = 0; a < h->dim; ++a) nm *= (size_t)(h->p + 1);
   h->ndof = 6 * (size_t)h->geo.E * nm;
-  h->rho_hat = spectral_constant_1d(h->p, h->geo.pen_c, h->geo.sym);
+  h->rho_hat = spectral_constant_1d(h->p, h->geo.pen_c, h->geo.sym, h->geo.wm, h->geo.wp);
   size_t bytes = h->ndof * (h->fp32 ? 4 : 8);
   for (int k = 0; k < 2; ++k) {
     if (hipMalloc(&h->stage[k], bytes) != hipSuccess) {

@@ -596,12 +596,15 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
       const T so = sg ? T(1) : T(-1);
       const T pen = T(g.pen_c * tb.liftc * g.ih[a]) * as;
       T G[NF], H[NF];
+      // weights of the own side and the neighbour in the average (own is K^- on the
+      // high face, sg = 1)
+      const T wo = T(sg ? g.wm : g.wp), wn = T(sg ? g.wp : g.wm);
 #pragma unroll
       for (int J = 0; J < NF; ++J) {
         T lin = T(0), hh = T(0);
         if (nb >= 0) {
-          lin = so * T(0.5) * as * (duo[J] + dun[J]) - pen * jm[J];
-          hh = T(0.5 * g.sym) * as * jm[J] * so * T(g.ih[a]);
+          lin = so * as * (wo * duo[J] + wn * dun[J]) - pen * jm[J];
+          hh = wo * T(g.sym) * as * jm[J] * so * T(g.ih[a]);
         }
         G[J] = ar * (lin + gh[J]);
         H[J] = ar * hh;

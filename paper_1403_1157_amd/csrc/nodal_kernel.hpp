@@ -452,10 +452,13 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
     // the jump and the derivative sum wait in LDS during the point pass (no
     // registers held through it)
     T* park = sm.buf + EB * S::NFQ * NF + tid * 2 * NF;
+    // weights of the own side and the neighbour in the average (own is K^- on the
+    // high face, sg = 1)
+    const T wo = T(sg ? g.wm : g.wp), wn = T(sg ? g.wp : g.wm);
 #pragma unroll
     for (int t = 0; t < NF; ++t) {
       park[t] = (m0 - w0) + (uo[t] - un[t]);
-      park[NF + t] = duo[t] + dun[t];
+      park[NF + t] = wo * duo[t] + wn * dun[t];
     }
     nd_sync();
     // face point pass
@@ -513,7 +516,7 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
       const T ar = T(g.area[a]);
       const T so = sg ? T(1) : T(-1);
       const T pen = T(g.pen_c * tb.liftc * g.ih[a]) * as;
-      const T hs = T(0.5 * g.sym) * as * so * T(g.ih[a]);
+      const T hs = T((sg ? g.wm : g.wp) * g.sym) * as * so * T(g.ih[a]);
       const bool in = nb >= 0;
       const T dw = T(diss ? 1 : 0);
       // the one flux slot this species adds: interior n1 F1 (1), n2 F2 (2);
@@ -528,7 +531,7 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
       for (int t = 0; t < NF; ++t) {
         const T jm = park[t], sd = park[NF + t];
         const T wa = ar * T(ct.w[t % Q] * ct.w[t / Q]);
-        const T gv = li * (so * T(0.5) * as * sd - (pen + dw * x[t]) * jm) + kw * x[ksl * NF + t];
+        const T gv = li * (so * as * sd - (pen + dw * x[t]) * jm) + kw * x[ksl * NF + t];
         const T G = wa * gv, H = li * wa * (hs * jm);
         // spread at once onto the normal line through the point
         R[face_mode<D, Q>(a, 0, t)] += le0 * G + dle0 * H;

@@ -36,6 +36,8 @@ struct Geo {
   double g1in[2];    // Gamma_{1,in} on the first tangential axis
   double pen_c;      // penalty factor: stabilisation pen_c (p+1)^2 a / h [[u]] (CDG2: chi_e = N/2)
   double sym;        // sign of the symmetry term {A grad phi}:[[U]] (-1: Baumann-Oden)
+  double wm, wp;     // weights of K^- and K^+ in the face average of A grad u.n (and of
+                     // the symmetry term): 1/2, 1/2 (central); 1, 0 (CDG: one-sided on K^-)
 };
 
 __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }

@@ -152,10 +152,11 @@ void build_tables(int p, Tables* t) {
   }
 }
 
-double spectral_constant_1d(int p, double pen_c, double sym) {
+double spectral_constant_1d(int p, double pen_c, double sym, double wm, double wp) {
   // Bilinear form of the 1D periodic diffusion operator on N = 8 unit cells:
-  // sum_K int u'v' - sum_e ({u'}[v] + sym {v'}[u]) + pen [u][v]; its largest
-  // singular value (the largest eigenvalue when the form is symmetric).
+  // sum_K int u'v' - sum_e ({u'}[v] + sym {v'}[u]) + pen [u][v], with the average
+  // {w'} = wm w'^- + wp w'^+; its largest singular value (the largest eigenvalue
+  // when the form is symmetric).
   Tables t;
   build_tables(p, &t);
   const int q = p + 1, N = 8, n = N * q;
@@ -172,10 +173,10 @@ double spectral_constant_1d(int p, double pen_c, double sym) {
     for (int i = 0; i < q; ++i) {
       idx[i] = L * q + i;
       jv[i] = t.E[1][i];
-      av[i] = 0.5 * t.dE[1][i];
+      av[i] = wm * t.dE[1][i];
       idx[q + i] = R * q + i;
       jv[q + i] = -t.E[0][i];
-      av[q + i] = 0.5 * t.dE[0][i];
+      av[q + i] = wp * t.dE[0][i];
     }
     for (int a = 0; a < 2 * q; ++a)
       for (int b = 0; b < 2 * q; ++b)

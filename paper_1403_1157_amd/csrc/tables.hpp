@@ -34,4 +34,4 @@ void build_tables(int p, Tables* t);
 
 // Spectral radius of the 1D periodic CDG2 diffusion operator with a = h = 1 and
 // lift factor chi_e (its penalty reduces to chi_e * liftc on Cartesian cells).
-double spectral_constant_1d(int p, double pen_c, double sym = 1.0);
+double spectral_constant_1d(int p, double pen_c, double sym = 1.0, double wm = 0.5, double wp = 0.5);

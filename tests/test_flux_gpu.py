@@ -1,5 +1,5 @@
 """GPU parity of the comparison diffusion fluxes (BR2, interior penalty,
-Baumann-Oden) against the oracle, through the C ABI."""
+Baumann-Oden, compact DG) against the oracle, through the C ABI."""
 import dataclasses
 
 import numpy as np
@@ -30,7 +30,10 @@ def gpu_op(cfg, precision="fp64"):
 CASES = [("br2", 3.0, 2, (5, 4), 2), ("ip", 5.0, 2, (5, 4), 2), ("bo", 0.0, 2, (5, 4), 2),
          ("ip", 0.0, 2, (4, 5), 4), ("bo", 0.0, 2, (6, 3), 1), ("br2", 0.0, 3, (3, 3, 2), 2),
          ("ip", 7.0, 3, (3, 2, 3), 1), ("bo", 0.0, 3, (2, 3, 3), 3), ("ip", 6.0, 3, (2, 3, 4), 2),
-         ("bo", 0.0, 3, (3, 4, 2), 2), ("bo", 0.0, 3, (3, 2, 2), 1)]
+         ("bo", 0.0, 3, (3, 4, 2), 2), ("bo", 0.0, 3, (3, 2, 2), 1),
+         ("cdg", 0.0, 2, (5, 4), 2), ("cdg", 0.0, 2, (4, 5), 4), ("cdg", 0.0, 2, (6, 3), 1),
+         ("cdg", 0.0, 3, (3, 3, 2), 2), ("cdg", 0.0, 3, (4, 3, 10), 2), ("cdg", 0.0, 3, (2, 3, 3), 3),
+         ("cdg", 0.0, 3, (3, 2, 2), 1)]
 
 
 @pytest.mark.parametrize("flux,eta,dim,n,p", CASES)
@@ -47,7 +50,7 @@ def test_flux_apply_parity(flux, eta, dim, n, p, precision):
     assert_close(out, ref, TOL[precision], f"{flux} d{dim} p{p} {precision}")
 
 
-@pytest.mark.parametrize("flux,eta", [("ip", 5.0), ("bo", 0.0)])
+@pytest.mark.parametrize("flux,eta", [("ip", 5.0), ("bo", 0.0), ("cdg", 0.0)])
 def test_flux_rk_steps_parity(flux, eta):
     U, cfg = make_case(2, (8, 6), 2, key=(11,), coeffs=strong())
     cfg = dataclasses.replace(cfg, diff_flux=flux, flux_eta=eta)
@@ -126,3 +129,18 @@ def test_br2_rk_step_adjoint_parity():
     got = dth.cpu().numpy()
     rel = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
     assert rel.max() <= 1e-11, rel.max()
+
+
+def test_compact_dg_cfl_constant_and_adjoint_rejection():
+    """The CFL constant of compact DG is the spectral radius of its 1D form (one-
+    sided average, penalty (p+1)^2): by its Bloch symbol in a monomial basis,
+    36.00, 148.26, 438.91, 1045.29 for p = 1..4.  The adjoint needs a central
+    flux and rejects it."""
+    from paper_1403_1157_amd.cdg2 import CDG2Error
+    want = {1: 36.0, 2: 148.25828965853387, 3: 438.90676544354307, 4: 1045.2915164466813}
+    for p, r in want.items():
+        U, cfg = make_case(2, (4, 4), p, key=(15,), coeffs=strong())
+        op = gpu_op(dataclasses.replace(cfg, diff_flux="cdg"))
+        assert abs(op.rho_hat - r) <= 1e-9 * r, (p, op.rho_hat)
+    with pytest.raises(CDG2Error):
+        op.apply_adjoint(U.to(DEV), U.to(DEV))

@@ -1,9 +1,11 @@
 """Pins of the oracle's comparison diffusion fluxes (BR2, interior penalty,
-Baumann-Oden) against the mathematics.  On uniform Cartesian cells the lifting
+Baumann-Oden, compact DG) against the mathematics.  On uniform Cartesian cells the lifting
 of a face jump has the same trace on both neighbours, so BR2 with eta = N and
 the interior penalty with eta = d reproduce CDG2; Baumann-Oden drops the
 stabilisation and flips the symmetry term, which makes its quadratic form the
-broken energy sum_K int a |grad u|^2."""
+broken energy sum_K int a |grad u|^2; compact DG (switch on K^-) has the quadratic
+form of the lifted gradient, sum_K int a |grad u + sum_e r~_e|^2 over the faces
+whose K^- is K."""
 import dataclasses
 import math
 
@@ -75,10 +77,39 @@ def test_baumann_oden_form_is_the_broken_energy():
         assert abs(quad - energy) < 1e-11 * energy
 
 
-@pytest.mark.parametrize("flux,eta,p,rho_mult", [("ip", 4.0, 1, 2.0), ("ip", 4.0, 2, 2.0), ("bo", 0.0, 1, 1.0)])
+def test_compact_dg_form_is_the_energy_of_the_lifted_gradient():
+    """CDG (one-sided on K^-, lifting of the whole jump onto K^-): for every u,
+    u^T A u = sum_K int_K a |grad u + sum_{e: K = K^-_e} r~_e|^2 with
+    int_K r~_e . tau = -int_e (u^- - u^+) n^- . tau (here: r~_e = n^- rho,
+    rho = -(1/|K|) sum_m phi_m int_e (u^- - u^+) phi_m for the orthonormal modes).
+    Liftings of different axes are orthogonal, so the form is semidefinite; a
+    wrong side, weight or lifting factor breaks the identity."""
+    a = 0.6
+    for dim, n, p in [(2, (3, 4), 2), (3, (3, 3, 2), 1)]:
+        cfg = Config(dim=dim, n=n, order=p, wall_axis=-1, coeffs=diffusion_only_coeffs(a), diff_flux="cdg")
+        o, A = _matrix(cfg)
+        assert float((A - A.T).abs().max()) < 1e-11 * float(A.abs().max())
+        for seed in range(2):
+            u = rand_state(o, seed)
+            quad = float(u.reshape(-1) @ (A @ u.reshape(-1)))
+            g = torch.einsum("sem,qmg->seqg", u, o.dPhi)               # grad u at the volume points
+            UG = o.grid(u)
+            lifted = g.clone()
+            for ax in range(dim):
+                F = o.faces[ax]
+                Up = torch.roll(UG, shifts=-1, dims=o.gdim(ax, 1))     # the K^+ neighbour
+                jump = torch.einsum("s...m,tm->s...t", UG, F["PhiHi"]) - torch.einsum("s...m,tm->s...t", Up, F["PhiLo"])
+                rho = -torch.einsum("t,s...t,tm->s...m", F["wf"], jump, F["PhiHi"]) / o.vol
+                lifted[..., ax] = lifted[..., ax] + torch.einsum("sem,qm->seq", o.flat(rho), o.Phi)
+            energy = float(a * torch.einsum("q,seqg->", o.wq, lifted * lifted))
+            assert abs(quad - energy) < 1e-11 * energy, (quad, energy)
+
+
+@pytest.mark.parametrize("flux,eta,p,rho_mult", [("ip", 4.0, 1, 2.0), ("ip", 4.0, 2, 2.0), ("bo", 0.0, 1, 1.0),
+                                                 ("cdg", 0.0, 1, 1.0), ("cdg", 0.0, 2, 1.0)])
 def test_comparison_fluxes_heat_equation_eoc(flux, eta, p, rho_mult):
-    """The exact heat solution of the CDG2 pin: IP converges with order p+1,
-    Baumann-Oden with odd p = 1 with order 2."""
+    """The exact heat solution of the CDG2 pin: IP and CDG converge with order
+    p+1, Baumann-Oden with odd p = 1 with order 2."""
     a, A0 = 0.05, 0.2
     lam = a * math.pi ** 2 * (4 + 1)
     rho_hat = {1: 84.0, 2: 362.06}[p] * rho_mult
