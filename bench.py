@@ -6,9 +6,14 @@ float64), inputs resident in HBM.  Prints ONE JSON line.
 
   value        operator GDOF/s = 3 * DOF * steps / seconds (three operator
                applications per step)
-  roofline     the fused stage kernel against the 8 TB/s HBM peak: algorithmic
-               bytes per step (64 B/DOF: stage 1 reads U and writes U1, stages 2
-               and 3 read two states and write one) / measured time per step
+  roofline     the fused stage kernels against the roof their counted arithmetic
+               intensity puts them under: FP64 flops per step (rocprofv3 SQ
+               counters, committed profile of the same sources) over the
+               algorithmic bytes per step (64 B/DOF: stage 1 reads U and writes
+               U1, stages 2 and 3 read two states and write one); above the
+               ridge (78.6 TFLOP/s / 8 TB/s) the FP64 roof, else HBM.  The HBM
+               fraction (algorithmic bytes / time / 8 TB/s) is reported beside it
+               in every case ("hbm"), and the FP64 utilisation ("fp64")
   cpu_baseline the float64 oracle (test infrastructure) timed on the host cores
                for one operator application of the same workload
 
@@ -38,8 +43,10 @@ WORKLOADS = {
     "2d-q2-256": (2, (256, 256), 2, (1,)),
     "2d-q4-256": (2, (256, 256), 4, (1,)),
     "2d-q1-16": (2, (16, 16), 1, (0,)),
+    "3d-q3-48": (3, (48, 48, 48), 3, (2,)),   # same DOF count as 3d-q2-64 (profiling the p = 3 kernel)
 }
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6    # vector FP64 (= matrix FP64 on gfx950)
 
 
 def kernel_source_hash() -> str:
@@ -52,9 +59,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(workload: str):
-    """HBM traffic per step from the committed rocprofv3 --pmc summary of this
-    workload, if it was taken on the current kernel sources; else None."""
+def read_profile(workload: str):
+    """HBM traffic and counted FP64 flops per step from the committed rocprofv3
+    --pmc summary of this workload, if it was taken on the current kernel
+    sources; else None."""
     path = os.path.join(ROOT, "profiles", f"op_kernel_{workload}_pmc.txt")
     if not os.path.exists(path):
         return None
@@ -66,7 +74,7 @@ def read_traffic(workload: str):
     if kv.get("source_hash") != kernel_source_hash():
         return None
     try:
-        return float(kv["bytes_per_step"])
+        return {"bytes_per_step": float(kv["bytes_per_step"]), "flops_per_step": float(kv["flops_per_step"])}
     except (KeyError, ValueError):
         return None
 
@@ -503,7 +511,25 @@ def main():
     value = 3 * dof / (ms_step * 1e-3) / 1e9
     alg_bytes_step = 64.0 * dof
     achieved = alg_bytes_step / (ms_step * 1e-3) / 1e9
-    traffic = read_traffic(args.workload)
+    prof = read_profile(args.workload)
+    traffic = prof["bytes_per_step"] if prof else None
+    hbm = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic}
+    roofline = dict(hbm)
+    if prof:
+        # counted FP64 flops of the stage kernels (rocprofv3 SQ counters): the
+        # arithmetic intensity against the algorithmic bytes decides the bound
+        intensity = prof["flops_per_step"] / alg_bytes_step
+        fp64_tf = prof["flops_per_step"] / (ms_step * 1e-3) / 1e12
+        fp64 = {"achieved_tflop_s": round(fp64_tf, 3), "peak_tflop_s": FP64_PEAK_TFS,
+                "frac": round(fp64_tf / FP64_PEAK_TFS, 4), "flop_per_dof_step": round(prof["flops_per_step"] / dof, 1),
+                "intensity_flop_per_byte": round(intensity, 2), "ridge_flop_per_byte": round(FP64_PEAK_TFS / HBM_PEAK_GBS * 1e3, 2)}
+        if intensity > FP64_PEAK_TFS / HBM_PEAK_GBS * 1e3:
+            roofline = {"bound": "alu", "achieved": round(fp64_tf, 3), "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                        "frac": round(fp64_tf / FP64_PEAK_TFS, 5), "traffic": traffic,
+                        "hbm_frac": hbm["frac"], "hbm_achieved_gb_s": hbm["achieved"]}
+    else:
+        fp64 = None
     line = {
         "metric": "CDG2 operator GDOF/s (SSP-RK3 stage applications, FP64)",
         "value": round(value, 4),
@@ -520,9 +546,9 @@ def main():
         "config": {"workload": f"{args.workload}: six-species CDG2 plaque model, "
                                f"{'x'.join(map(str, n))} cells, Q{p}, one SSP-RK3 step",
                    "dim": dim, "cells": list(n), "order": p, "dof": dof, "dt": dt},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": traffic},
+        "roofline": roofline,
+        "hbm": hbm,
+        "fp64": fp64,
         "trials_ms_per_step": {"median": round(trials[2], 5), "min": round(trials[0], 5),
                                "max": round(trials[-1], 5)},
         "copy_gb_s": round(copy_gbs, 1),

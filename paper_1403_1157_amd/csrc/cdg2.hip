@@ -164,8 +164,16 @@ hipError_t launch_op(cdg2_handle* h, const void* U, const void* U0, void* out, d
   int nb = (h->geo.E + EB - 1) / EB;
   // nodal form for 3D p <= 2; 3D p = 3 keeps the modal kernel (register budget)
   if constexpr (D == 3 && P <= 2) {
-    hipLaunchKernelGGL((nd_kernel<P, T, EB>), dim3(nb), dim3(6 * EB), 0, h->stream, h->dprm, (const T*)U,
-                       (const T*)U0, (T*)out, (T)dt, (T)ca, (T)cb, stage, h->flags);
+    // one kernel per launch kind: apply, stage without u0, stage with u0
+    if (stage == 0)
+      hipLaunchKernelGGL((nd_kernel<P, T, EB, 0>), dim3(nb), dim3(6 * EB), 0, h->stream, h->dprm, (const T*)U,
+                         (const T*)U0, (T*)out, (T)dt, (T)ca, (T)cb, h->flags);
+    else if (ca == 0.0)
+      hipLaunchKernelGGL((nd_kernel<P, T, EB, 1>), dim3(nb), dim3(6 * EB), 0, h->stream, h->dprm, (const T*)U,
+                         (const T*)U0, (T*)out, (T)dt, (T)ca, (T)cb, h->flags);
+    else
+      hipLaunchKernelGGL((nd_kernel<P, T, EB, 2>), dim3(nb), dim3(6 * EB), 0, h->stream, h->dprm, (const T*)U,
+                         (const T*)U0, (T*)out, (T)dt, (T)ca, (T)cb, h->flags);
   } else {
     hipLaunchKernelGGL((es_kernel<D, P, T, EB>), dim3(nb), dim3(6 * EB), 0, h->stream, h->dprm,
                        (const T*)U, (const T*)U0, (T*)out, (T)dt, (T)ca, (T)cb, stage, h->flags);

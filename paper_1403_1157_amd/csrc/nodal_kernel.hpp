@@ -191,10 +191,13 @@ __device__ __forceinline__ void nd_sync() {
   __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int P, typename T, int EB>
+// KIND: 0 an operator application (out = f(U)); 1 an SSP-RK3 stage without the
+// u0 term (out = cb (U + dt f(U))); 2 a stage with it (out = ca U0 + cb (U + dt f(U))).
+// Each kind is its own kernel (the profiles tell them apart, and the branches of
+// the other kinds are not compiled in).
+template <int P, typename T, int EB, int KIND>
 __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict__ U, const T* U0, T* out, T dt,
-                                         T ca, T cb, int stage, int* __restrict__ flags, int e0,
-                                         NdSmem<P, T, EB>& sm) {
+                                         T ca, T cb, int* __restrict__ flags, int e0, NdSmem<P, T, EB>& sm) {
   constexpr int D = 3;
   using S = EsSz<D, P>;
   constexpr int Q = S::Q, NM = S::NM, NF = S::NF, NFACE = S::NFACE, PC = S::PC;
@@ -545,13 +548,13 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
   // the u0 values this thread will store are requested first, so that their
   // latency overlaps the transform back to modes
   constexpr int IT = store_slots<EB, NM>();
-  const bool combine = stage != 0 && ca != T(0);
+  constexpr bool combine = KIND == 2;
   T u0[IT];
   if (combine) load_u0_chunk<T, EB, NM, IT>(sm.cell, U0, SE, tid, 0, u0);
   {
     const T ivol = T(1.0 / g.vol);
     T z[NM], y[NM];
-    if (stage == 0) {
+    if constexpr (KIND == 0) {
 #pragma unroll
       for (int m = 0; m < NM; ++m) z[m] = R[m] * ivol;
     } else {
@@ -569,23 +572,23 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
           }
     }
     nd_tapply3<Q, true, T>(z, y);
-    if (stage != 0) y[0] += m0;
+    if constexpr (KIND != 0) y[0] += m0;
     nd_sync();
 #pragma unroll
-    for (int m = 0; m < NM; ++m) sm.buf[tid * NM + m] = stage == 0 ? y[m] : cb * y[m];
+    for (int m = 0; m < NM; ++m) sm.buf[tid * NM + m] = KIND == 0 ? y[m] : cb * y[m];
   }
   nd_sync();
   store_chunk<T, EB, NM, IT>(sm.cell, sm.buf, u0, out, SE, ca, combine, tid, 0, flag);
   if (flag) atomicOr(flags, flag);
 }
 
-template <int P, typename T, int EB>
+template <int P, typename T, int EB, int KIND>
 __global__ void __launch_bounds__(6 * EB, 2)
 nd_kernel(const Params* __restrict__ prm, const T* __restrict__ U, const T* U0, T* out, T dt, T ca, T cb,
-          int stage, int* __restrict__ flags) {
+          int* __restrict__ flags) {
   __shared__ NdSmem<P, T, EB> sm;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
-  nd_block<P, T, EB>(*prm, U, U0, out, dt, ca, cb, stage, flags, blk * EB, sm);
+  nd_block<P, T, EB, KIND>(*prm, U, U0, out, dt, ca, cb, flags, blk * EB, sm);
 }
 
 }  // namespace cdg2
