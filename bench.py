@@ -18,8 +18,9 @@ float64), inputs resident in HBM.  Prints ONE JSON line.
                for one operator application of the same workload
 
 Extras in the same line (skipped with --no-extras): the 256^2 Q2/Q4 workloads
-(graph-replayed applies, 100-step runs), the batched 256-instance run against
-the plain entry point, the adjoint (forward + gradient against forward), the
+(graph-replayed applies, 100-step runs), the batched 256-instance run (autotuned
+schedule and the best single persistent launch) against the plain entry point
+(eager and graph-replayed), the adjoint (forward + gradient against forward), the
 implicit SDIRK step against the explicit steps over the same interval, the
 comparison diffusion fluxes on the exact heat solution, and the unstructured
 triangle (P1-P3) and tetrahedral (P2, P3; the size of the paper's 3D run) meshes.
@@ -140,8 +141,9 @@ def time_ms(fn, reps=1):
 
 def bench_batched(steps=50):
     """256 independent 2D instances (grid side 32..128, order 1..3, coefficients
-    within +-50%): one persistent launch per stage, graph-replayed, autotuned,
-    against 256 sequential plain per-instance rk_step runs of the same instances."""
+    within +-50%): the autotuned schedule (graph-replayed), the best single
+    persistent launch per stage, against 256 sequential plain per-instance
+    rk_step runs of the same instances, eager and replayed from one graph."""
     import torch
 
     from paper_1403_1157_amd import inputs
@@ -165,6 +167,19 @@ def bench_batched(steps=50):
     bt.sync()
     ms_b = time_ms(lambda: bt.rk(work, dts, steps))
     bt.sync()
+    # the single persistent launch per stage over the cost-sorted work list (one
+    # launch for all orders, a fixed number of workgroups), best of a few sizes
+    ncu = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    pers = None
+    for eb, mult in ((32, 1), (32, 2), (32, 4), (64, 2)):
+        bt.set_schedule(eb, mult * ncu, 0)
+        bt.rk(work, dts, steps)
+        bt.sync()
+        ms = time_ms(lambda: bt.rk(work, dts, steps))
+        bt.sync()
+        if pers is None or ms < pers[1]:
+            pers = ((eb, mult * ncu, 0), ms)
+    bt.set_schedule(*tune["schedule"])
     plain = [U.clone() for U in states]
 
     def run_plain():
@@ -173,15 +188,42 @@ def bench_batched(steps=50):
 
     run_plain()
     ms_p = time_ms(run_plain)
+    # the same plain launches replayed from one captured graph (no launch overhead)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run_plain()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        run_plain()
+    graph.replay()
+    torch.cuda.synchronize()
+    ms_pg = time_ms(graph.replay)
+    del graph
     for op in ops:
         op.sync()
         op.close()
     bt.close()
-    return {"instances": 256, "steps": steps, "dof": dof, "schedule": tune["schedule"],
-            "ms_batched": round(ms_b, 3), "ms_plain_sequential": round(ms_p, 3),
-            "speedup_vs_plain": round(ms_p / ms_b, 3),
+    sched = tune["schedule"]
+    return {"instances": 256, "steps": steps, "dof": dof,
+            "schedule": sched,
+            "schedule_meaning": ("one launch per polynomial order and stage (three per stage, side by side on "
+                                 "forked streams), " + ("one workgroup per work item" if sched[1] == 0 else
+                                                        f"{sched[1]} persistent workgroups each")
+                                 if sched[2] == 2 else
+                                 ("one launch per stage over the " + ("cost-sorted" if sched[2] == 0 else "instance-ordered")
+                                  + " work list, " + ("one workgroup per work item" if sched[1] == 0 else
+                                                      f"{sched[1]} persistent workgroups"))),
+            "ms_batched": round(ms_b, 3),
+            "persistent_single_launch": {"schedule": list(pers[0]), "ms": round(pers[1], 3),
+                                         "meaning": "one launch per stage for all orders over the cost-sorted list, "
+                                                    f"{pers[0][1]} persistent workgroups"},
+            "ms_plain_sequential": round(ms_p, 3), "ms_plain_graph": round(ms_pg, 3),
+            "speedup_vs_plain": round(ms_p / ms_b, 3), "speedup_vs_plain_graph": round(ms_pg / ms_b, 3),
             "gdof_steps_per_s_batched": round(dof * steps / (ms_b * 1e-3) / 1e9, 3),
-            "gdof_steps_per_s_plain": round(dof * steps / (ms_p * 1e-3) / 1e9, 3)}
+            "gdof_steps_per_s_plain": round(dof * steps / (ms_p * 1e-3) / 1e9, 3),
+            "batched_hbm_frac": round(64.0 * dof * steps / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def bench_adjoint(steps=200, ckpt=20):

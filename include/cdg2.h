@@ -260,10 +260,12 @@ int cdg2_rk_adjoint_segment(cdg2_handle* h, const void* U_start, int nsteps, dou
 
 /* ---- batched instances ---------------------------------------------------------
  * Many independent 2D instances (own grid, order 1..3, coefficients; FP64) are
- * advanced together: one persistent launch per SSP-RK3 stage walks a work list
- * of (instance, block of cells) items in a schedule set by
- * cdg2_batch_set_schedule; cdg2_batch_rk replays the stages of nsteps steps as
- * one HIP graph.  The packed state holds instance i at element offset
+ * advanced together; the schedule (cdg2_batch_set_schedule, or the autotuner)
+ * decides the launches of an SSP-RK3 stage: one launch over the whole work list
+ * of (instance, block of cells) items, either persistent (nwg > 0 workgroups
+ * walk the list) or one workgroup per item (nwg = 0), or one launch per
+ * polynomial order (order 2, side by side on forked streams).  cdg2_batch_rk
+ * replays the stages of nsteps steps as one HIP graph.  The packed state holds instance i at element offset
  * cdg2_batch_offset(b, i), each in the DOF layout above. */
 typedef struct cdg2_batch cdg2_batch;
 
@@ -354,10 +356,10 @@ int cdg2_tri_sync(cdg2_tri* t);
  * M_K = |K| I; Gram-Schmidt, for the mean over the reference tetrahedron (0,0,0),
  * (1,0,0), (0,1,0), (0,0,1), of the monomials xi^a eta^b zeta^c ordered by total
  * degree, then by the power of zeta, then of eta, taken about the centroid);
- * volume integrals with the collapsed Gauss rule of (k+2)(k+1)^2 points, face
- * integrals with a fully symmetric triangle rule of degree 2k (3, 6, 12 points;
- * its orbit parameters solve the moment equations) so that both elements of a
- * face use the same points; LLF and CDG2 fluxes (lifting on K^-: the smaller
+ * volume integrals with a fully symmetric rule on the tetrahedron of degree 2k
+ * (4, 14, 24 points), face integrals with a fully symmetric triangle rule of
+ * degree 2k (3, 6, 12 points; the orbit parameters of both solve the moment
+ * equations) so that both elements of a face use the same points; LLF and CDG2 fluxes (lifting on K^-: the smaller
  * tetrahedron of a face, ties to the lower element index; chi_e = 2) and the
  * inflow fluxes of eqs. (7)-(9) on the faces coded Gamma1 / Gamma2.  State
  * layout: U[6][E][(k+1)(k+2)(k+3)/6] doubles, species n1, n2, n3, c1, c2, c3.

@@ -15,9 +15,11 @@ the residual <phi_j, L_h(U)> of the six-species model of Section 2 with
     eta^2, xi zeta, eta zeta, zeta^2, ...), taken about the centroid (every
     prefix spans the same space as the plain monomials; far less cancellation);
     so phi_0 = 1 (mode 0 is the element mean) and M_K = |K| I;
-  * volume integrals with the collapsed Gauss rule xi = u, eta = v (1 - u),
-    zeta = w (1 - u)(1 - v), weight (1 - u)^2 (1 - v), with k + 2 points in u
-    and k + 1 in v and w: exact for total degree 2k (the mass matrix);
+  * volume integrals with a fully symmetric rule on the tetrahedron exact for
+    degree 2k (the mass matrix): k = 1: 4 points, degree 2; k = 2: 14 points,
+    degree 4; k = 3: 24 points, degree 6; orbits of the vertex permutations
+    with positive weights, their parameters solving the moment equations
+    (Newton, here);
   * face integrals with a fully symmetric rule on the triangle, exact for
     degree 2k (k = 1: 3 points, degree 2; k = 2: 6 points, degree 4; k = 3:
     12 points, degree 6), so that both elements of a face use the same physical
@@ -75,6 +77,103 @@ def collapsed_tet_rule(k: int):
                 pts.append((u[i], v[j] * (1 - u[i]), w[l] * (1 - u[i]) * (1 - v[j])))
                 wts.append(wu[i] * wv[j] * ww[l] * (1 - u[i]) ** 2 * (1 - v[j]))
     return np.array(pts), np.array(wts)
+
+
+def _tet_mean(a, b, c, d):
+    """Mean of l0^a l1^b l2^c l3^d over a tetrahedron (barycentric coordinates)."""
+    f = math.factorial
+    return 6.0 * f(a) * f(b) * f(c) * f(d) / f(a + b + c + d + 3)
+
+
+def symmetric_tet_rule(k: int):
+    """Fully symmetric rule on the tetrahedron exact for degree 2k (k = 2: 5), as
+    barycentric points [n, 4] and weights [n] for the mean (sum 1).  Orbits of the
+    vertex permutations: (a, a, a, 1 - 3a) with 4 points, (b, b, 1/2 - b, 1/2 - b)
+    with 6, (b, b, c, 1 - 2b - c) with 12.  k = 1: one 4-orbit; k = 2: two 4-orbits
+    and a 6-orbit; k = 3: three 4-orbits and a 12-orbit.  The orbit parameters and
+    all but the last weight solve the moment equations of every monomial up to
+    that degree (least-squares Newton from rough starting values).  For k = 2 the
+    14-point layout has one parameter more than the symmetric moment equations of
+    degree 4 fix, a one-parameter family of rules; degree 5 leaves the one rule of
+    that layout.  The solution must be isolated (Jacobian of full column rank), so
+    that any solver of the same equations finds the same rule."""
+    if k == 1:
+        layout, x = [("s31", 1)], [0.14]
+    elif k == 2:
+        layout, x = [("s31", 1), ("s31", 1), ("s22", 1)], [0.093, 0.073, 0.311, 0.113, 0.045]
+    elif k == 3:
+        layout, x = ([("s31", 1), ("s31", 1), ("s31", 1), ("s211", 2)],
+                     [0.215, 0.24, 0.041, 0.06, 0.322, 0.33, 0.064, 0.27])
+    else:
+        raise ValueError("volume rules for k = 1, 2, 3")
+
+    def orbit(kind, q):
+        if kind == "s31":
+            base = (q[0], q[0], q[0], 1 - 3 * q[0])
+        elif kind == "s22":
+            base = (q[0], q[0], 0.5 - q[0], 0.5 - q[0])
+        else:
+            base = (q[0], q[0], q[1], 1 - 2 * q[0] - q[1])
+        return sorted(set(permutations(base)))
+
+    def expand(y):
+        groups, i, used = [], 0, 0.0
+        for o, (kind, npar) in enumerate(layout):
+            pts = orbit(kind, y[i:i + npar])
+            i += npar
+            if o < len(layout) - 1:
+                w = y[i]
+                i += 1
+                used += len(pts) * w
+            else:
+                w = None
+            groups.append((pts, w))
+        pts, _ = groups[-1]
+        groups[-1] = (pts, (1.0 - used) / len(pts))
+        P = np.array([p for pts, w in groups for p in pts], dtype=np.float64)
+        W = np.array([w for pts, w in groups for p in pts], dtype=np.float64)
+        return P, W
+
+    deg = tet_rule_degree(k)
+    mons = [(a, b, c, d - a - b - c) for d in range(deg + 1) for a in range(d + 1)
+            for b in range(d - a + 1) for c in range(d - a - b + 1)]
+
+    def resid(y):
+        P, W = expand(y)
+        return np.array([np.sum(W * P[:, 0] ** a * P[:, 1] ** b * P[:, 2] ** c * P[:, 3] ** d) - _tet_mean(a, b, c, d)
+                         for a, b, c, d in mons])
+
+    def jac(y):
+        Jm = np.zeros((len(mons), len(y)))
+        for i in range(len(y)):
+            e = np.zeros(len(y))
+            e[i] = 1e-7
+            Jm[:, i] = (resid(y + e) - resid(y - e)) / 2e-7
+        return Jm
+
+    x = np.array(x, dtype=np.float64)
+    for _ in range(100):
+        r = resid(x)
+        if np.abs(r).max() < 1e-15:
+            break
+        x = x - np.linalg.lstsq(jac(x), r, rcond=None)[0]
+    P, W = expand(x)
+    assert np.abs(resid(x)).max() < 1e-14, "volume rule did not converge"
+    sv = np.linalg.svd(jac(x), compute_uv=False)
+    assert sv[-1] > 1e-6 * sv[0], "volume rule is not an isolated solution"
+    return P, W
+
+
+def tet_rule_degree(k: int) -> int:
+    """Polynomial degree of the volume rule of order k: 2k, but 5 for k = 2."""
+    return 5 if k == 2 else 2 * k
+
+
+def tet_volume_rule(k: int):
+    """The operator's volume rule: reference points [n, 3] (xi, eta, zeta) =
+    barycentric coordinates of vertices 1, 2, 3, and weights [n] (sum 1/6)."""
+    P, W = symmetric_tet_rule(k)
+    return P[:, 1:4].copy(), W / 6.0
 
 
 def _tri_mean(a, b, c):
@@ -253,7 +352,7 @@ class TetOracle:
         self.gamma1_in = gamma1_in
         self.basis = TetBasis(order)
         self.nb = self.basis.nb
-        pts, wts = collapsed_tet_rule(order)
+        pts, wts = tet_volume_rule(order)
         self.Bv = torch.tensor(self.basis.values(pts), dtype=DT)
         self.Bg = torch.tensor(self.basis.grads(pts), dtype=DT)
         self.wv = torch.tensor(6.0 * wts, dtype=DT)                      # mean weights

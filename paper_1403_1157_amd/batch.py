@@ -1,4 +1,4 @@
-"""Batched instances: packed state, persistent-launch SSP-RK3 and its autotuner.
+"""Batched instances: packed state, batched SSP-RK3 launches and their autotuner.
 
 The arithmetic runs in libcdg2 (cdg2_batch_*), and so does the schedule search
 (cdg2_batch_autotune times every candidate: cells per work item, persistent

@@ -151,13 +151,159 @@ int tet_face_rule(int k, double (*bary)[3], double* wts) {
   return build(x, bary, wts);
 }
 
+// Fully symmetric rule on the tetrahedron exact for degree D = 2k, but D = 5 for
+// k = 2 (barycentric points, weights for the mean): orbits of the vertex
+// permutations (a, a, a, 1-3a) of 4 points, (b, b, 1/2-b, 1/2-b) of 6,
+// (b, b, c, 1-2b-c) of 12; k = 1: one 4-orbit; k = 2: two 4-orbits and a 6-orbit;
+// k = 3: three 4-orbits and a 12-orbit.  The orbit parameters and all but the
+// last weight solve the moment equations of the monomials l1^a l2^b l3^c
+// (a + b + c <= D, mean 6 a! b! c! / (a+b+c+3)!) by Gauss-Newton from rough
+// starting values.  Degree 4 leaves the 14-point layout a one-parameter family
+// of rules; degree 5 isolates one, so the rule does not depend on the solver.
+// Returns the number of points, or -1 if the equations are not met to rounding
+// level.
+int tet_volume_rule(int k, double (*bary)[4], double* wts) {
+  enum { S31, S22, S211 };
+  int kinds[4], norb;
+  double x[10];
+  int nx;
+  if (k == 1) {
+    norb = 1;
+    kinds[0] = S31;
+    x[0] = 0.14;
+    nx = 1;
+  } else if (k == 2) {
+    norb = 3;
+    kinds[0] = S31;
+    kinds[1] = S31;
+    kinds[2] = S22;
+    const double g[5] = {0.093, 0.073, 0.311, 0.113, 0.045};   // a1, w1, a2, w2, b
+    std::memcpy(x, g, sizeof g);
+    nx = 5;
+  } else {
+    norb = 4;
+    kinds[0] = S31;
+    kinds[1] = S31;
+    kinds[2] = S31;
+    kinds[3] = S211;
+    const double g[8] = {0.215, 0.24, 0.041, 0.06, 0.322, 0.33, 0.064, 0.27};   // a_i, w_i; b, c
+    std::memcpy(x, g, sizeof g);
+    nx = 8;
+  }
+  auto build = [&](const double* y, double (*P)[4], double* W) {
+    int n = 0, i = 0;
+    double used = 0.0;
+    for (int o = 0; o < norb; ++o) {
+      double base[4];
+      if (kinds[o] == S31) {
+        const double a = y[i++];
+        base[0] = base[1] = base[2] = a;
+        base[3] = 1 - 3 * a;
+      } else if (kinds[o] == S22) {
+        const double b = y[i++];
+        base[0] = base[1] = b;
+        base[2] = base[3] = 0.5 - b;
+      } else {
+        const double b = y[i], c = y[i + 1];
+        i += 2;
+        base[0] = base[1] = b;
+        base[2] = c;
+        base[3] = 1 - 2 * b - c;
+      }
+      // the distinct permutations of base
+      double pts[24][4];
+      int m = 0;
+      std::sort(base, base + 4);
+      do {
+        for (int q = 0; q < 4; ++q) pts[m][q] = base[q];
+        ++m;
+      } while (std::next_permutation(base, base + 4));
+      double w;
+      if (o < norb - 1) {
+        w = y[i++];
+        used += m * w;
+      } else {
+        w = (1.0 - used) / m;
+      }
+      for (int r = 0; r < m; ++r) {
+        for (int q = 0; q < 4; ++q) P[n][q] = pts[r][q];
+        W[n++] = w;
+      }
+    }
+    return n;
+  };
+  std::vector<std::array<int, 3>> mons;
+  const int deg = k == 2 ? 5 : 2 * k;
+  for (int d = 0; d <= deg; ++d)
+    for (int a = 0; a <= d; ++a)
+      for (int b = 0; b <= d - a; ++b) mons.push_back({a, b, d - a - b});
+  const int ne = (int)mons.size();
+  auto resid = [&](const double* y, double* r) {
+    double P[24][4], W[24];
+    const int n = build(y, P, W);
+    for (int q = 0; q < ne; ++q) {
+      double acc = 0.0;
+      for (int p = 0; p < n; ++p)
+        acc += W[p] * std::pow(P[p][1], mons[q][0]) * std::pow(P[p][2], mons[q][1]) * std::pow(P[p][3], mons[q][2]);
+      r[q] = acc - 6.0 * fact(mons[q][0]) * fact(mons[q][1]) * fact(mons[q][2]) /
+                       fact(mons[q][0] + mons[q][1] + mons[q][2] + 3);
+    }
+  };
+  std::vector<double> r(ne), rp(ne), rm(ne), Jm((size_t)ne * nx);
+  bool ok = false;
+  for (int it = 0; it < 100; ++it) {
+    resid(x, r.data());
+    double mx = 0.0;
+    for (double v : r) mx = std::fmax(mx, std::fabs(v));
+    if (mx < 1e-15) {
+      ok = true;
+      break;
+    }
+    for (int j = 0; j < nx; ++j) {
+      double xp[10], xm[10];
+      std::memcpy(xp, x, sizeof x);
+      std::memcpy(xm, x, sizeof x);
+      xp[j] += 1e-7;
+      xm[j] -= 1e-7;
+      resid(xp, rp.data());
+      resid(xm, rm.data());
+      for (int q = 0; q < ne; ++q) Jm[(size_t)q * nx + j] = (rp[q] - rm[q]) / 2e-7;
+    }
+    double A[10][11] = {};
+    for (int a = 0; a < nx; ++a) {
+      for (int b = 0; b < nx; ++b)
+        for (int q = 0; q < ne; ++q) A[a][b] += Jm[(size_t)q * nx + a] * Jm[(size_t)q * nx + b];
+      for (int q = 0; q < ne; ++q) A[a][nx] += Jm[(size_t)q * nx + a] * r[q];
+    }
+    for (int col = 0; col < nx; ++col) {
+      int piv = col;
+      for (int row = col + 1; row < nx; ++row)
+        if (std::fabs(A[row][col]) > std::fabs(A[piv][col])) piv = row;
+      for (int cc = 0; cc <= nx; ++cc) std::swap(A[col][cc], A[piv][cc]);
+      for (int row = 0; row < nx; ++row) {
+        if (row == col) continue;
+        const double fct = A[row][col] / A[col][col];
+        for (int cc = col; cc <= nx; ++cc) A[row][cc] -= fct * A[col][cc];
+      }
+    }
+    for (int j = 0; j < nx; ++j) x[j] -= A[j][nx] / A[j][j];
+  }
+  if (!ok) {
+    resid(x, r.data());
+    double mx = 0.0;
+    for (double v : r) mx = std::fmax(mx, std::fabs(v));
+    if (mx > 1e-14) return -1;
+  }
+  return build(x, bary, wts);
+}
+
 // Orthonormal basis of P_k on the reference tetrahedron for the mean: modified
 // Gram-Schmidt of the monomials xi^a eta^b zeta^c (total degree, then power of
 // zeta, then of eta), taken about the centroid (1/4, 1/4, 1/4) -- every prefix
 // spans the same space as the plain monomials, with far less cancellation --
 // under a collapsed Gauss rule exact for the products; then the values and
-// gradients at the volume rule ((k+2)(k+1)^2 collapsed Gauss points) and at the
-// points of the symmetric face rule on each local face.
+// gradients at the points of the symmetric volume rule and of the symmetric face
+// rule on each local face.
 int build_tet_tables(int k, TetTables* t) {
   std::memset(t, 0, sizeof(TetTables));
   int pw[TET_MAXB][3], nb = 0;
@@ -242,15 +388,18 @@ int build_tet_tables(int k, TetTables* t) {
       gd[j][2] = b2;
     }
   };
-  collapsed(k + 2, k + 1, P, W);
-  for (size_t q = 0; q < P.size(); ++q) {
+  double vb[24][4], vw[24];
+  const int nq = tet_volume_rule(k, vb, vw);
+  if (nq != TetSz<3>::NQ && nq != TetSz<2>::NQ && nq != TetSz<1>::NQ) return -1;
+  for (int q = 0; q < nq; ++q) {
+    const double X[3] = {vb[q][1], vb[q][2], vb[q][3]};   // (xi, eta, zeta): coordinates of vertices 1, 2, 3
     double v[TET_MAXB], gd[TET_MAXB][3];
-    basis(P[q].data(), v, gd);
+    basis(X, v, gd);
     for (int j = 0; j < nb; ++j) {
       t->Bv[q][j] = v[j];
       for (int a = 0; a < 3; ++a) t->Bg[q][j][a] = gd[j][a];
     }
-    t->wv[q] = W[q];
+    t->wv[q] = vw[q];
   }
   double bary[TET_MAXF][3], fw[TET_MAXF];
   const int nf = tet_face_rule(k, bary, fw);

@@ -3,8 +3,8 @@
 //
 // The discrete operator (Section 3.1 on tetrahedra, the element of the paper's 3D
 // runs): basis phi_j = phi^_j o F_K^-1 with phi^_j orthonormal on the reference
-// tetrahedron for the mean (phi_0 = 1, M_K = |K| I); volume integrals with the
-// collapsed Gauss rule of (k+2)(k+1)^2 points (exact for degree 2k); face
+// tetrahedron for the mean (phi_0 = 1, M_K = |K| I); volume integrals with a
+// fully symmetric rule of 4, 14, 24 points (exact for degree 2k); face
 // integrals with a fully symmetric triangle rule of degree 2k, so both elements
 // of a face evaluate at the same physical points: the neighbour's point index is
 // the own index under one of the six vertex permutations (orientation, host
@@ -33,7 +33,7 @@
 namespace cdg2 {
 
 constexpr int TET_MAXB = 20;   // P_3
-constexpr int TET_MAXQ = 80;   // (k + 2)(k + 1)^2 volume points
+constexpr int TET_MAXQ = 24;   // points of the symmetric volume rule (degree 2k)
 constexpr int TET_MAXF = 12;   // points of the symmetric face rule (degree 2k)
 constexpr int TET_EB = 32;     // elements per workgroup (192 threads)
 
@@ -75,9 +75,9 @@ constexpr int tet_face_points(int K) { return K == 1 ? 3 : K == 2 ? 6 : 12; }
 
 template <int K>
 struct TetSz {
-  static constexpr int NB = (K + 1) * (K + 2) * (K + 3) / 6, NQ = (K + 2) * (K + 1) * (K + 1);
+  static constexpr int NB = (K + 1) * (K + 2) * (K + 3) / 6, NQ = K == 1 ? 4 : K == 2 ? 14 : 24;
   static constexpr int NF = tet_face_points(K);
-  static constexpr int QC = K == 3 ? 8 : 6;   // volume points per LDS chunk
+  static constexpr int QC = K == 1 ? 4 : K == 2 ? 7 : 8;   // volume points per LDS chunk
   static_assert(NQ % QC == 0, "volume chunks");
   // volume slots: 0 n1 1 n2 2 c1 3 c3 | 4..6 grad n1 | 7..9 grad c1 | 10..12 grad c3 | 13 n3 14 c2
   static constexpr int NVQ = 15;

@@ -54,7 +54,7 @@ def test_struct_layout_matches_header():
 @pytest.mark.parametrize("field,value", [
     ("dim", 4), ("dim", 1), ("order", 0), ("order", 5), ("n0", 1), ("wall_axis", 3),
     ("wall_axis", -2), ("precision", 7), ("llf_mode", 3), ("g1", (0.8, 0.2)),
-    ("nan", None), ("neg_diff", None), ("order3d", 4), ("flux", 4), ("flux", -1), ("eta", -1.0),
+    ("nan", None), ("neg_diff", None), ("order3d", 4), ("flux", 5), ("flux", -1), ("eta", -1.0),
     ("eta", float("inf"))])
 def test_invalid_config_rejected(field, value):
     c = inputs.base_coeffs()

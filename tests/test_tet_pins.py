@@ -11,7 +11,8 @@ import pytest
 import torch
 
 from oracle.tet_oracle import (FACE_VERTS, TetBasis, TetMesh, TetOracle, collapsed_tet_rule,
-                               symmetric_face_rule)
+                               symmetric_face_rule, symmetric_tet_rule, tet_rule_degree,
+                               tet_volume_rule)
 from paper_1403_1157_amd import inputs
 
 
@@ -77,15 +78,37 @@ def test_basis_orthonormal_and_mean_mode(k):
 
 
 @pytest.mark.parametrize("k", [1, 2, 3])
-def test_volume_rule_exact_to_degree_2k(k):
-    p, w = collapsed_tet_rule(k)
-    assert abs(6.0 * w.sum() - 1.0) < 1e-15
-    for d in range(2 * k + 1):
+def test_volume_rule_symmetric_exact_positive(k):
+    """The operator's volume rule: exact for every monomial of degree <= 2k (k = 2:
+    5, which makes the 14-point rule unique) in the barycentric coordinates (mean
+    6 a! b! c! d! / (a + b + c + d + 3)!), mapped onto itself by every permutation
+    of the vertices, positive weights, points inside; 4, 14, 24 points.  In
+    reference coordinates it integrates the monomials of the reference
+    tetrahedron exactly too."""
+    P, W = symmetric_tet_rule(k)
+    assert len(W) == {1: 4, 2: 14, 3: 24}[k]
+    assert tet_rule_degree(k) == {1: 2, 2: 5, 3: 6}[k]
+    assert (W > 0).all() and (P > 0).all() and abs(W.sum() - 1.0) < 1e-15
+    f = math.factorial
+    for d in range(tet_rule_degree(k) + 1):
         for a in range(d + 1):
-            for bb in range(d - a + 1):
-                c = d - a - bb
-                got = 6.0 * np.sum(w * p[:, 0] ** a * p[:, 1] ** bb * p[:, 2] ** c)
-                assert abs(got - _tet_monomial_mean(a, bb, c)) < 1e-14, (a, bb, c)
+            for b in range(d - a + 1):
+                for c in range(d - a - b + 1):
+                    e = d - a - b - c
+                    got = np.sum(W * P[:, 0] ** a * P[:, 1] ** b * P[:, 2] ** c * P[:, 3] ** e)
+                    assert abs(got - 6.0 * f(a) * f(b) * f(c) * f(e) / f(d + 3)) < 1e-15
+    for perm in permutations(range(4)):
+        Q = P[:, list(perm)]
+        for q, wq in zip(Q, W):
+            i = np.argmin(np.abs(P - q).sum(axis=1))
+            assert np.abs(P[i] - q).max() < 1e-15 and abs(W[i] - wq) < 1e-16
+    p, w = tet_volume_rule(k)
+    for d in range(tet_rule_degree(k) + 1):
+        for a in range(d + 1):
+            for b in range(d - a + 1):
+                c = d - a - b
+                got = 6.0 * np.sum(w * p[:, 0] ** a * p[:, 1] ** b * p[:, 2] ** c)
+                assert abs(got - _tet_monomial_mean(a, b, c)) < 1e-14, (a, b, c)
 
 
 @pytest.mark.parametrize("k", [1, 2, 3])
