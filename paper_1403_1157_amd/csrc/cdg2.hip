@@ -151,6 +151,15 @@ void build_geo(const cdg2_config& c, Geo* g) {
 
 // ---- launch dispatch ----------------------------------------------------------
 
+// Launch codes of run_op: 0 an operator application; 1, 2, 3 the SSP-RK3 stages
+// (modes in and out); STAGE_POINTS1 + 0, 1, 2 the stages of a step whose
+// intermediate states are point values (3D p <= 2 only: modes -> points,
+// points -> points, points -> modes).
+constexpr int STAGE_POINTS1 = 11;
+
+// The SSP-RK3 step of rk_steps keeps its intermediate states as point values.
+bool point_stages(const cdg2_handle* h) { return h->dim == 3 && h->p <= 2; }
+
 // cells per workgroup of the (cell, species) kernel: 6 * EB threads
 template <int D, int P>
 struct EsCfg {
@@ -164,17 +173,26 @@ hipError_t launch_op(cdg2_handle* h, const void* U, const void* U0, void* out, d
   int nb = (h->geo.E + EB - 1) / EB;
   // nodal form for 3D p <= 2; 3D p = 3 keeps the modal kernel (register budget)
   if constexpr (D == 3 && P <= 2) {
-    // one kernel per launch kind: apply, stage without u0, stage with u0
-    if (stage == 0)
-      hipLaunchKernelGGL((nd_kernel<P, T, EB, 0>), dim3(nb), dim3(6 * EB), 0, h->stream, h->dprm, (const T*)U,
-                         (const T*)U0, (T*)out, (T)dt, (T)ca, (T)cb, h->flags);
-    else if (ca == 0.0)
-      hipLaunchKernelGGL((nd_kernel<P, T, EB, 1>), dim3(nb), dim3(6 * EB), 0, h->stream, h->dprm, (const T*)U,
-                         (const T*)U0, (T*)out, (T)dt, (T)ca, (T)cb, h->flags);
-    else
-      hipLaunchKernelGGL((nd_kernel<P, T, EB, 2>), dim3(nb), dim3(6 * EB), 0, h->stream, h->dprm, (const T*)U,
-                         (const T*)U0, (T*)out, (T)dt, (T)ca, (T)cb, h->flags);
+    // one kernel per launch kind: apply, stage without u0, stage with u0 (modes
+    // in and out); the three stages of a step with point-value intermediates
+    const int kind = stage == 0 ? 0 : stage >= STAGE_POINTS1 ? 3 + stage - STAGE_POINTS1 : ca == 0.0 ? 1 : 2;
+    switch (kind) {
+#define CDG2_ND_LAUNCH(KD)                                                                                  \
+  case KD:                                                                                                   \
+    hipLaunchKernelGGL((nd_kernel<P, T, EB, KD>), dim3(nb), dim3(6 * EB), 0, h->stream, h->dprm, (const T*)U, \
+                       (const T*)U0, (T*)out, (T)dt, (T)ca, (T)cb, h->flags);                                \
+    break;
+      CDG2_ND_LAUNCH(0)
+      CDG2_ND_LAUNCH(1)
+      CDG2_ND_LAUNCH(2)
+      CDG2_ND_LAUNCH(3)
+      CDG2_ND_LAUNCH(4)
+      CDG2_ND_LAUNCH(5)
+#undef CDG2_ND_LAUNCH
+      default: return hipErrorInvalidValue;
+    }
   } else {
+    if (stage >= STAGE_POINTS1) return hipErrorInvalidValue;   // the modal kernel has no point-value stages
     hipLaunchKernelGGL((es_kernel<D, P, T, EB>), dim3(nb), dim3(6 * EB), 0, h->stream, h->dprm,
                        (const T*)U, (const T*)U0, (T*)out, (T)dt, (T)ca, (T)cb, stage, h->flags);
   }
@@ -349,11 +367,14 @@ void* scratch_device(int device) {
 }
 
 // nsteps fused SSP-RK3 steps on U with the intermediate states in st0, st1.
+// On the nodal 3D path the two intermediate states are point values (the
+// stage kernels of kinds 3 to 5); the states the adjoint recomputes stay modes.
 int rk_steps(cdg2_handle* h, void* U, double dt, int nsteps, void* st0, void* st1) {
+  const int k0 = point_stages(h) ? STAGE_POINTS1 : 1;
   for (int n = 0; n < nsteps; ++n) {
-    HIP_TRY(run_op(h, U, nullptr, st0, dt, 0.0, 1.0, 1));
-    HIP_TRY(run_op(h, st0, U, st1, dt, 0.75, 0.25, 2));
-    HIP_TRY(run_op(h, st1, U, U, dt, 1.0 / 3.0, 2.0 / 3.0, 3));
+    HIP_TRY(run_op(h, U, nullptr, st0, dt, 0.0, 1.0, k0));
+    HIP_TRY(run_op(h, st0, U, st1, dt, 0.75, 0.25, k0 + 1));
+    HIP_TRY(run_op(h, st1, U, U, dt, 1.0 / 3.0, 2.0 / 3.0, k0 + 2));
   }
   return CDG2_OK;
 }

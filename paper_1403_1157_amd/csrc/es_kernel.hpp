@@ -77,34 +77,89 @@ struct EsSmem {
   __align__(16) T buf[N];
 };
 
-// Element m of thread g's staged modes.
+// Rotation of the chunks of the cell in workgroup slot l, and the position (in
+// units of LS bytes) of chunk j of thread g = (species, cell l = g mod EB): the
+// thread's NCH chunks are contiguous, rotated by (l / 2) mod NCH.  Unrotated, the
+// threads' chunk j would sit NCH positions apart, which maps most lanes of a
+// wavefront onto a few LDS banks; with the rotation and whole-chunk reads the
+// banks are hit at most 1.5 times as often as without conflicts, for the chunk
+// sizes used here.  The rotation depends on the cell only, so the loads need one
+// rotated chunk index per lane and round, not one per species.
+template <int NCH>
+__device__ __forceinline__ int stage_rot(int l) {
+  return (l >> 1) % NCH;
+}
+
+template <int NCH, int EB>
+__device__ __forceinline__ int stage_pos(int g, int j) {
+  int c = j + stage_rot<NCH>(g % EB);
+  if (c >= NCH) c -= NCH;
+  return g * NCH + c;
+}
+
+// Element m of thread g's staged values.
 template <int D, int P, typename T, int EB, int NV, int XT>
 __device__ __forceinline__ T staged(const EsSmem<D, P, T, EB, NV, XT>& sm, int g, int m) {
   using SM = EsSmem<D, P, T, EB, NV, XT>;
   constexpr int CB = SM::CB, NCH = SM::NCH, LS = SM::LS;
   const unsigned char* base = reinterpret_cast<const unsigned char*>(sm.buf);
-  if constexpr (LS == CB) {   // contiguous segments
-    return *reinterpret_cast<const T*>(base + g * SM::BYTES + m * (int)sizeof(T));
-  } else {
-    const int b = m * (int)sizeof(T), j = b / CB, r = b % CB;
-    if (r + (int)sizeof(T) <= CB) {
-      return *reinterpret_cast<const T*>(base + (g * NCH + j) * LS + r);
-    } else {   // a double split over two chunks, 4 + 4 bytes
-      const int lo = *reinterpret_cast<const int*>(base + (g * NCH + j) * LS + r);
-      const int hi = *reinterpret_cast<const int*>(base + (g * NCH + j + 1) * LS);
-      return T(__hiloint2double(hi, lo));
-    }
+  const int b = m * (int)sizeof(T), j = b / CB, r = b % CB;
+  if (r + (int)sizeof(T) <= CB) {
+    return *reinterpret_cast<const T*>(base + stage_pos<NCH, EB>(g, j) * LS + r);
+  } else {   // a double split over two chunks, 4 + 4 bytes
+    const int lo = *reinterpret_cast<const int*>(base + stage_pos<NCH, EB>(g, j) * LS + r);
+    const int hi = *reinterpret_cast<const int*>(base + stage_pos<NCH, EB>(g, j + 1) * LS);
+    return T(__hiloint2double(hi, lo));
   }
 }
 
-// Start loading the modes of the workgroup's cells sm.cell[l] (outside [0, E):
-// none, cell 0 is loaded and not used) of all six species straight into the
-// staging area, without registers in flight: consecutive lanes take consecutive
-// chunks, so each load instruction reads whole cache lines of consecutive cells
-// (one lane per cell and 216-byte modes would put every lane on its own line).
-// The caller waits (vmcnt) and synchronises before reading.
+// All NM staged values of thread g, read chunk by chunk (one 16-, 12- or 4-byte
+// LDS read per chunk) and reassembled in registers.
 template <int D, int P, typename T, int EB, int NV, int XT>
-__device__ __forceinline__ void stage_modes(const T* U, size_t SE, int E, EsSmem<D, P, T, EB, NV, XT>& sm, int tid) {
+__device__ __forceinline__ void staged_all(const EsSmem<D, P, T, EB, NV, XT>& sm, int g, T* u) {
+  using SM = EsSmem<D, P, T, EB, NV, XT>;
+  constexpr int CB = SM::CB, NCH = SM::NCH, LS = SM::LS, NW = SM::BYTES / 4, NM = EsSz<D, P>::NM;
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+  const unsigned char* base = reinterpret_cast<const unsigned char*>(sm.buf);
+  unsigned int w[NW];
+#pragma unroll
+  for (int j = 0; j < NCH; ++j) {
+    const unsigned char* src = base + stage_pos<NCH, EB>(g, j) * LS;
+    if constexpr (CB == 16) {
+      const u32x4 x = *reinterpret_cast<const u32x4*>(src);
+      w[4 * j] = x.x;
+      w[4 * j + 1] = x.y;
+      w[4 * j + 2] = x.z;
+      w[4 * j + 3] = x.w;
+    } else if constexpr (CB == 12) {
+      const u32x3 x = *reinterpret_cast<const u32x3*>(src);
+      w[3 * j] = x.x;
+      w[3 * j + 1] = x.y;
+      w[3 * j + 2] = x.z;
+    } else {
+      w[j] = *reinterpret_cast<const unsigned int*>(src);
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    if constexpr (sizeof(T) == 8)
+      u[m] = T(__hiloint2double((int)w[2 * m + 1], (int)w[2 * m]));
+    else
+      u[m] = T(__uint_as_float(w[m]));
+  }
+}
+
+// Start loading the values of the cells cells[l * cstride] (l < EB; outside
+// [0, E): none, cell 0 is loaded and not used) of all six species straight into
+// the staging area, without registers in flight: consecutive lanes take
+// consecutive chunks of one cell, so each load instruction reads whole cache
+// lines of consecutive cells (one lane per cell and 216-byte modes would put
+// every lane on its own line).  The caller waits (vmcnt) and synchronises before
+// reading.
+template <int D, int P, typename T, int EB, int NV, int XT>
+__device__ __forceinline__ void stage_cells(const T* U, size_t SE, int E, const int* cells, int cstride,
+                                            EsSmem<D, P, T, EB, NV, XT>& sm, int tid) {
   using SM = EsSmem<D, P, T, EB, NV, XT>;
   constexpr int NM = EsSz<D, P>::NM, NT = 6 * EB, CB = SM::CB, NCH = SM::NCH;
   static_assert(SM::BYTES % CB == 0, "chunking");
@@ -116,10 +171,13 @@ __device__ __forceinline__ void stage_modes(const T* U, size_t SE, int E, EsSmem
   const int wbase = __builtin_amdgcn_readfirstlane((tid / 64) * 64);
 #pragma unroll
   for (int r = 0; r < RR; ++r) {
-    const int ch = r * NT + tid;
+    const int ch = r * NT + tid;   // position within the species block
     if (ch < PER) {
-      const int l = ch / NCH, k = ch % NCH;
-      const int n = sm.cell[l];
+      const int l = ch / NCH, c = ch % NCH;
+      const int n = cells[l * cstride];
+      // the chunk that belongs at this position (inverse of stage_pos)
+      int k = c - stage_rot<NCH>(l);
+      if (k < 0) k += NCH;
       const char* src = reinterpret_cast<const char*>(U + (size_t)(n >= 0 && n < E ? n : 0) * NM) + k * CB;
 #pragma unroll
       for (int sp = 0; sp < 6; ++sp) {
@@ -135,6 +193,12 @@ __device__ __forceinline__ void stage_modes(const T* U, size_t SE, int E, EsSmem
       }
     }
   }
+}
+
+// The workgroup's own cells sm.cell[l].
+template <int D, int P, typename T, int EB, int NV, int XT>
+__device__ __forceinline__ void stage_modes(const T* U, size_t SE, int E, EsSmem<D, P, T, EB, NV, XT>& sm, int tid) {
+  stage_cells<D, P, T, EB>(U, SE, E, sm.cell, 1, sm, tid);
 }
 
 __device__ __forceinline__ void wait_staged() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
@@ -296,8 +360,9 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
     stage_modes<D, P, T, EB>(U, SE, E, sm, tid);
     wait_staged();
     __syncthreads();
+    staged_all<D, P, T, EB>(sm, tid, u);
 #pragma unroll
-    for (int m = 0; m < NM; ++m) u[m] = live ? staged<D, P, T, EB>(sm, tid, m) : T(0);
+    for (int m = 0; m < NM; ++m) u[m] = live ? u[m] : T(0);
   } else {
     const T* src = U + s * SE + (size_t)e * NM;
 #pragma unroll

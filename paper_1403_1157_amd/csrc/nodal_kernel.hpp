@@ -173,6 +173,34 @@ __device__ __forceinline__ void nd_tapply3(const T* in, T* out) {
     }
 }
 
+// u <- (B (x) B (x) B) u in place, one line of Q entries at a time along each
+// axis (only Q temporaries live).
+template <int Q, typename T>
+__device__ __forceinline__ void nd_tapply3_inplace(T* u) {
+  constexpr NdTab<Q> ct = nd_tab<Q>();
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const int st = ax == 0 ? 1 : ax == 1 ? Q : Q * Q;
+#pragma unroll
+    for (int b = 0; b < Q; ++b)
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        // the line through (a, b) of the two other axes
+        const int o = ax == 0 ? Q * a + Q * Q * b : ax == 1 ? a + Q * Q * b : a + Q * b;
+        T t[Q];
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+          T acc = T(0);
+#pragma unroll
+          for (int i = 0; i < Q; ++i) nd_acc(acc, ct.B[c][i], u[o + st * i]);
+          t[c] = acc;
+        }
+#pragma unroll
+        for (int c = 0; c < Q; ++c) u[o + st * c] = t[c];
+      }
+  }
+}
+
 // Volume exchange slots per point: 0 n1, 1 n2, 2 c1, 3 c3, 4..6 grad n1,
 // 7..9 grad c1, 10..12 grad c3, 13 n3, 14 c2.  The point items overwrite
 // 4..6 with F1 (weighted, / h_a), 7..9 with F2 and 10 with the alpha term.
@@ -193,6 +221,18 @@ __device__ __forceinline__ void nd_sync() {
 
 // KIND: 0 an operator application (out = f(U)); 1 an SSP-RK3 stage without the
 // u0 term (out = cb (U + dt f(U))); 2 a stage with it (out = ca U0 + cb (U + dt f(U))).
+// Kinds 0 to 2 read and write modes.  Kinds 3 to 5 are the stages of an SSP-RK3
+// step whose two intermediate states are kept as point values (the coefficients
+// of the Lagrange basis of the Gauss points, same layout as the modes: point
+// i + Q (j + Q k) where mode i + Q (j + Q k) would be):
+//   3  stage 1, modes in, point values out, out = cb (U + dt f(U));
+//   4  stage 2, point values in and out, out = ca U0 + cb (U + dt f(U)) with U0
+//      given as modes and taken to the points in the kernel;
+//   5  stage 3, point values in, modes out, out = ca U0 + cb (U + dt f(U)).
+// The point values of an intermediate state are what the kernel computes first
+// anyway, and a neighbour's traces from them cost one contraction along the
+// normal (three terms per face point) instead of that and two tangential
+// transforms; the three stages make the same discrete step up to rounding.
 // Each kind is its own kernel (the profiles tell them apart, and the branches of
 // the other kinds are not compiled in).
 template <int P, typename T, int EB, int KIND>
@@ -218,6 +258,9 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
   const T vol = T(g.vol);
   int flag = 0;
 
+  constexpr bool nodal_in = KIND == 4 || KIND == 5;
+  constexpr bool nodal_out = KIND == 3 || KIND == 4;
+
   // ---- own modes -> nodal values --------------------------------------------------
   T v[NM], R[NM], m0;
   if (tid < EB) sm.cell[tid] = e0 + tid < E ? cell_of<D>(g, e0 + tid) : -1;
@@ -230,7 +273,16 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
   }
   wait_staged();
   nd_sync();
-  {
+  if constexpr (nodal_in) {
+    // point values as stored (their rounding is already that of the full values,
+    // so no mean is kept apart)
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      const T x = staged<D, P, T, EB>(sm, tid, m);
+      v[m] = live ? x : T(0);
+    }
+    m0 = T(0);
+  } else {
     T u[NM];
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
@@ -397,32 +449,50 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
     nd_sync();
     const int nb = sm.nb[el][f];
     // traces at the face points: own from the nodal values (end values of the
-    // Lagrange functions along the normal), neighbour from its modes.  The side's
-    // end values come from the run-time tables: selected among compile-time
-    // constants, the compiler formed both sides' products and kept them live.
+    // Lagrange functions along the normal), neighbour from its values in global
+    // memory.  The side's end values come from the run-time tables: selected
+    // among compile-time constants, the compiler formed both sides' products and
+    // kept them live.
     T uo[NF], duo[NF], un[NF], dun[NF];
     T w0;   // neighbour mean (mode 0); un, dun are its fluctuation's traces
     {
       // a boundary face reads the own cell (in range) and weighs it by zero
       const T inner = T(nb >= 0 ? 1 : 0);
       const T* un_src = U + s * SE + (size_t)(nb >= 0 ? nb : sm.cell[el] >= 0 ? sm.cell[el] : 0) * NM;
-      T mv[NF], md[NF];
+      if constexpr (nodal_in) {
+        // the neighbour's point values on the normal lines through the face points
 #pragma unroll
-      for (int J = 0; J < NF; ++J) {
-        T a0 = T(0), a1 = T(0);
+        for (int t = 0; t < NF; ++t) {
+          T a0 = T(0), a1 = T(0);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          const int m = face_mode<D, Q>(a, i, J);
-          const T x = un_src[m];
-          if (m != 0) a0 += T(tb.E[1 - sg][i]) * x;   // the mean apart
-          if (i != 0) a1 += T(tb.dE[1 - sg][i]) * x;  // phi_0' = 0
+          for (int i = 0; i < Q; ++i) {
+            const T x = un_src[face_mode<D, Q>(a, i, t)];
+            a0 += T(tb.Le[1 - sg][i]) * x;
+            a1 += T(tb.dLe[1 - sg][i]) * x;
+          }
+          un[t] = a0 * inner;
+          dun[t] = a1 * (inner * T(g.ih[a]));
         }
-        mv[J] = a0 * inner;
-        md[J] = a1 * (inner * T(g.ih[a]));
+        w0 = T(0);
+      } else {
+        T mv[NF], md[NF];
+#pragma unroll
+        for (int J = 0; J < NF; ++J) {
+          T a0 = T(0), a1 = T(0);
+#pragma unroll
+          for (int i = 0; i < Q; ++i) {
+            const int m = face_mode<D, Q>(a, i, J);
+            const T x = un_src[m];
+            if (m != 0) a0 += T(tb.E[1 - sg][i]) * x;   // the mean apart
+            if (i != 0) a1 += T(tb.dE[1 - sg][i]) * x;  // phi_0' = 0
+          }
+          mv[J] = a0 * inner;
+          md[J] = a1 * (inner * T(g.ih[a]));
+        }
+        nd_tapply2<Q, false, T>(mv, un);
+        nd_tapply2<Q, false, T>(md, dun);
+        w0 = un_src[0] * inner;
       }
-      nd_tapply2<Q, false, T>(mv, un);
-      nd_tapply2<Q, false, T>(md, dun);
-      w0 = un_src[0] * inner;
     }
 #pragma unroll
     for (int t = 0; t < NF; ++t) {
@@ -545,13 +615,38 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
   }
 
   // ---- back to modes: M^{-1}, stage combination, coalesced store ------------------------
-  // the u0 values this thread will store are requested first, so that their
-  // latency overlaps the transform back to modes
-  constexpr int IT = store_slots<EB, NM>();
-  constexpr bool combine = KIND == 2;
-  T u0[IT];
-  if (combine) load_u0_chunk<T, EB, NM, IT>(sm.cell, U0, SE, tid, 0, u0);
-  {
+  // (+ ca U0 in the store, whose U0 loads come in chunks: all of them in flight
+  // through the transform back would not fit the register budget)
+  constexpr bool combine = KIND == 2 || KIND == 5;
+  if constexpr (nodal_out) {
+    // point values: M = |K| W_q is diagonal in the Lagrange basis of the points
+    const T dti = dt * T(1.0 / g.vol);
+    T y[NM];
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+#pragma unroll
+      for (int j = 0; j < Q; ++j)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const int m = i + Q * (j + Q * k);
+          y[m] = cb * ((m0 + v[m]) + dti * R[m] * T(1.0 / (ct.w[i] * ct.w[j] * ct.w[k])));
+        }
+    if constexpr (KIND == 4) {
+      // + ca U0 at the points: the workgroup's U0 modes through the staging area
+      nd_sync();
+      stage_modes<D, P, T, EB>(U0, SE, E, sm, tid);
+      wait_staged();
+      nd_sync();
+      T u[NM];
+      staged_all<D, P, T, EB>(sm, tid, u);
+      nd_tapply3_inplace<Q, T>(u);
+#pragma unroll
+      for (int m = 0; m < NM; ++m) y[m] += ca * u[m];
+    }
+    nd_sync();
+#pragma unroll
+    for (int m = 0; m < NM; ++m) sm.buf[tid * NM + m] = y[m];
+  } else {
     const T ivol = T(1.0 / g.vol);
     T z[NM], y[NM];
     if constexpr (KIND == 0) {
@@ -578,7 +673,7 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
     for (int m = 0; m < NM; ++m) sm.buf[tid * NM + m] = KIND == 0 ? y[m] : cb * y[m];
   }
   nd_sync();
-  store_chunk<T, EB, NM, IT>(sm.cell, sm.buf, u0, out, SE, ca, combine, tid, 0, flag);
+  store_results<T, EB, NM>(sm.cell, sm.buf, U0, out, SE, ca, combine, tid, flag);
   if (flag) atomicOr(flags, flag);
 }
 

@@ -83,8 +83,12 @@ def test_rk_step_adjoint_parity(dim, n, p):
 @pytest.mark.parametrize("dim,n,p,nsteps", [(2, (8, 6), 2, 7), (2, (5, 6), 3, 1), (3, (4, 3, 4), 2, 3)])
 def test_adjoint_segment_matches_step_adjoints(dim, n, p, nsteps):
     """cdg2_rk_adjoint_segment against nsteps calls of cdg2_rk_step_adjoint on the
-    states of the same forward run: the same kernels on the same inputs, so lam
-    agrees to rounding-free equality up to the parameter sums' order (dtheta)."""
+    states of the same forward run.  In 2D (and 3D p = 3) the segment's forward
+    recomputation and cdg2_rk_step run the same kernels on the same inputs, so lam
+    agrees to rounding-free equality up to the parameter sums' order (dtheta).  On
+    the nodal 3D path (p <= 2) cdg2_rk_step keeps its intermediate states as point
+    values while the segment recomputes modal stage states for the adjoint: the
+    forward states agree to rounding, so lam does to a rounding-level bound."""
     c = strong()
     U, cfg = make_case(dim, n, p, key=(6,), coeffs=c)
     op = gpu_op(cfg)
@@ -105,8 +109,13 @@ def test_adjoint_segment_matches_step_adjoints(dim, n, p, nsteps):
     dth = torch.zeros(21, dtype=torch.float64, device=DEV)
     op.rk_adjoint_segment(Ud, nsteps, dt, lam, dth)
     op.sync()
-    assert torch.equal(lam, lam_ref)
-    theta_close(dth.cpu().numpy(), dth_ref.cpu().numpy(), 1e-13)
+    if dim == 3 and p <= 2:
+        err = float((lam - lam_ref).abs().max()) / float(lam_ref.abs().max())
+        assert err < 1e-13, err
+        theta_close(dth.cpu().numpy(), dth_ref.cpu().numpy(), 1e-11)
+    else:
+        assert torch.equal(lam, lam_ref)
+        theta_close(dth.cpu().numpy(), dth_ref.cpu().numpy(), 1e-13)
     # a second, longer segment on the same handle grows the workspace
     lam2 = lam0.clone()
     op.rk_adjoint_segment(Ud, nsteps + 2, dt, lam2)
