@@ -207,9 +207,13 @@ __device__ __forceinline__ void nd_tapply3_inplace(T* u) {
 constexpr int ND_NVQ = 15;
 
 // After the face slots: each thread's face jump and derivative sum (2 x NF
-// values), parked there through the face point pass.
+// values), parked there through the face point pass.  The per-thread stride
+// stays 2 NF (16-byte aligned, so two values move in one LDS access): an odd
+// stride, free of bank conflicts, measured slower.
+template <int P>
+constexpr int nd_park_stride() { return 2 * (P + 1) * (P + 1); }
 template <int P, typename T, int EB>
-using NdSmem = EsSmem<3, P, T, EB, ND_NVQ, 6 * EB * 2 * (P + 1) * (P + 1)>;
+using NdSmem = EsSmem<3, P, T, EB, ND_NVQ, 6 * EB * nd_park_stride<P>()>;
 
 // Workgroup barrier that is also a scheduling fence: no instruction moves across
 // it, so the compiler cannot start a later layer's or face's arithmetic early and
@@ -243,7 +247,7 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
   constexpr int Q = S::Q, NM = S::NM, NF = S::NF, NFACE = S::NFACE, PC = S::PC;
   constexpr int NVQ = ND_NVQ, NT = 6 * EB;
   static_assert(NdSmem<P, T, EB>::STAGED, "3D staging");
-  static_assert(EB * NVQ * PC <= NdSmem<P, T, EB>::N && EB * S::NFQ * NF + NT * 2 * NF <= NdSmem<P, T, EB>::N &&
+  static_assert(EB * NVQ * PC <= NdSmem<P, T, EB>::N && EB * S::NFQ * NF + NT * nd_park_stride<P>() <= NdSmem<P, T, EB>::N &&
                     NT * NM <= NdSmem<P, T, EB>::N,
                 "LDS union");
   const Tables& tb = prm.tb;
@@ -524,7 +528,7 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
     }
     // the jump and the derivative sum wait in LDS during the point pass (no
     // registers held through it)
-    T* park = sm.buf + EB * S::NFQ * NF + tid * 2 * NF;
+    T* park = sm.buf + EB * S::NFQ * NF + tid * nd_park_stride<P>();
     // weights of the own side and the neighbour in the average (own is K^- on the
     // high face, sg = 1)
     const T wo = T(sg ? g.wm : g.wp), wn = T(sg ? g.wp : g.wm);
@@ -599,7 +603,7 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
       const T li = T(in ? 1 : 0);   // linear face terms on interior faces only
       const T le0 = T(tb.Le[sg][0]), le1 = T(tb.Le[sg][1]), dle0 = T(tb.dLe[sg][0]), dle1 = T(tb.dLe[sg][1]);
       const T le2 = T(tb.Le[sg][Q - 1]), dle2 = T(tb.dLe[sg][Q - 1]);
-      const T* park = sm.buf + EB * S::NFQ * NF + tid * 2 * NF;
+      const T* park = sm.buf + EB * S::NFQ * NF + tid * nd_park_stride<P>();
 #pragma unroll
       for (int t = 0; t < NF; ++t) {
         const T jm = park[t], sd = park[NF + t];

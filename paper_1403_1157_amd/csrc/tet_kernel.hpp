@@ -90,13 +90,22 @@ struct TetSz {
 template <int K>
 constexpr bool tet_ftab_in_lds() { return K <= 2; }
 
+// Per-element (and per-thread) strides of the LDS slots, odd in doubles: the
+// plain strides (15 QC, 14 NF, 2 NF doubles) put the 32 elements of a species on
+// 2 to 16 banks (up to a 16-way conflict); odd strides spread them over all.
+template <int K>
+struct TetStride {
+  using S = TetSz<K>;
+  static constexpr int VS = S::NVQ * S::QC + 1, FS = S::NFQ * S::NF + 1, PS = 2 * S::NF + 1;
+};
+
 template <int K>
 struct TetSmem {
   using S = TetSz<K>;
-  static constexpr int VOL = TET_EB * S::NVQ * S::QC, FAC = TET_EB * S::NFQ * S::NF;
+  static constexpr int VOL = TET_EB * TetStride<K>::VS, FAC = TET_EB * TetStride<K>::FS;
   static constexpr int N = VOL > FAC ? VOL : FAC;
   double buf[N];
-  double park[6 * TET_EB * 2 * S::NF];   // each thread's face jump and normal-derivative sum
+  double park[6 * TET_EB * TetStride<K>::PS];   // each thread's face jump and normal-derivative sum
   double ftab[tet_ftab_in_lds<K>() ? 4 * S::NF * S::NB * 4 : 1];   // [face][point][mode][4]
 };
 
@@ -106,7 +115,8 @@ __global__ void __launch_bounds__(6 * TET_EB, 2)
 tet_kernel(const TetParams* __restrict__ prm, const double* __restrict__ U, const double* U0, double* out,
            double dt, double ca, double cb, int stage, int* __restrict__ flags) {
   using S = TetSz<K>;
-  constexpr int NB = S::NB, NQ = S::NQ, NF = S::NF, QC = S::QC, NVQ = S::NVQ, NT = 6 * TET_EB;
+  constexpr int NB = S::NB, NQ = S::NQ, NF = S::NF, QC = S::QC, NT = 6 * TET_EB;
+  constexpr int VS = TetStride<K>::VS, FS = TetStride<K>::FS, PS = TetStride<K>::PS;
   __shared__ TetSmem<K> sm;
   const TetTables& tb = prm->tb;
   const TetGeo& g = prm->g;
@@ -142,7 +152,7 @@ tet_kernel(const TetParams* __restrict__ prm, const double* __restrict__ U, cons
   const double as = c[K_MU1 + s];
 
   // ---- volume, QC points at a time ---------------------------------------------------
-  double* V = sm.buf;   // [EB][NVQ][QC]
+  double* V = sm.buf;   // [EB][VS]: NVQ slots of QC points, then one pad
   const int vslot = s == S_N1 ? 0 : s == S_N2 ? 1 : s == S_C1 ? 2 : s == S_C3 ? 3 : s == S_N3 ? 13 : 14;
   const int gslot = s == S_N1 ? 4 : s == S_C1 ? 7 : s == S_C3 ? 10 : -1;
   // linear reactions: n1 -d1 n1; n2 -d2 n2; n3 (d1 - gamma) n1 + d2 n2; c1 f1 n3 (+ alpha
@@ -157,7 +167,7 @@ tet_kernel(const TetParams* __restrict__ prm, const double* __restrict__ U, cons
   for (int q0 = 0; q0 < NQ; q0 += QC) {
     __syncthreads();
     {
-      double* o = V + el * NVQ * QC;
+      double* o = V + el * VS;
 #pragma unroll 1
       for (int qq = 0; qq < QC; ++qq) {
         const int q = q0 + qq;
@@ -180,7 +190,7 @@ tet_kernel(const TetParams* __restrict__ prm, const double* __restrict__ U, cons
     // point items: chemotactic fluxes F1 (slots 4..6), F2 (7..9), alpha term (10)
     for (int it = tid; it < TET_EB * QC; it += NT) {
       const int l = it / QC, qq = it % QC;
-      double* x = V + l * NVQ * QC + qq;
+      double* x = V + l * VS + qq;
       const double n1 = x[0], n2 = x[QC], c1 = x[2 * QC], c3 = x[3 * QC];
       const double d11 = c1 + c[K_XT11], d13 = c3 + c[K_XT13], d21 = c1 + c[K_XT21], d22 = n1 + c[K_XT22];
       if (e0 + l < E && !(d11 > 0.0 && d13 > 0.0 && d21 > 0.0 && d22 > 0.0)) flag |= FLAG_DOMAIN;
@@ -206,7 +216,7 @@ tet_kernel(const TetParams* __restrict__ prm, const double* __restrict__ U, cons
     {
       // test integration; the own gradient is formed again here rather than held
       // in registers through the exchange
-      const double* x = V + el * NVQ * QC;
+      const double* x = V + el * VS;
 #pragma unroll 1
       for (int qq = 0; qq < QC; ++qq) {
         const int q = q0 + qq;
@@ -235,13 +245,13 @@ tet_kernel(const TetParams* __restrict__ prm, const double* __restrict__ U, cons
   }
 
   // ---- faces ----------------------------------------------------------------------
-  double* Fx = sm.buf;   // [EB][NFQ][NF]
+  double* Fx = sm.buf;   // [EB][FS]: NFQ slots of NF points, then one pad
   const double* ft;
   if constexpr (tet_ftab_in_lds<K>())
     ft = sm.ftab;
   else
     ft = &tb.ftab[0][0][0][0];
-  double* park = sm.park + tid * 2 * NF;
+  double* park = sm.park + tid * PS;
   const int fvslot = s == S_N1 ? 0 : s == S_N2 ? 1 : s == S_C1 ? 2 : s == S_C3 ? 3 : -1;
   const int dslot = s == S_N1 ? 8 : s == S_C1 ? 9 : s == S_C3 ? 10 : -1;
 #pragma unroll 1
@@ -293,19 +303,19 @@ tet_kernel(const TetParams* __restrict__ prm, const double* __restrict__ U, cons
       park[p] = uo - un;
       park[NF + p] = dno + dnn;
       if (fvslot >= 0) {
-        Fx[(el * 14 + fvslot) * NF + p] = uo;
-        Fx[(el * 14 + 4 + fvslot) * NF + p] = un;
+        Fx[el * FS + fvslot * NF + p] = uo;
+        Fx[el * FS + (4 + fvslot) * NF + p] = un;
       }
       if (dslot >= 0) {
-        Fx[(el * 14 + dslot) * NF + p] = dno;
-        Fx[(el * 14 + dslot + 3) * NF + p] = dnn;
+        Fx[el * FS + dslot * NF + p] = dno;
+        Fx[el * FS + (dslot + 3) * NF + p] = dnn;
       }
     }
     __syncthreads();
     // face point items: lambda / 2, -(F1 + F1').n / 2, -(F2 + F2').n / 2, or inflow
     for (int it = tid; it < TET_EB * NF; it += NT) {
       const int l = it / NF, p = it % NF;
-      double* x = Fx + l * 14 * NF + p;
+      double* x = Fx + l * FS + p;
       const int el2 = e0 + l;
       const int nbl = el2 < E ? g.nbr[4 * el2 + f] : -3;
       const double c1o = x[2 * NF];
@@ -354,7 +364,7 @@ tet_kernel(const TetParams* __restrict__ prm, const double* __restrict__ U, cons
     // species pass: every face term at the face points, weighted, spread onto the
     // own basis at once
     if (live) {
-      const double* x = Fx + el * 14 * NF;
+      const double* x = Fx + el * FS;
       const double ar = g.area[4 * e + f];
       const bool mine = g.minus[4 * e + f] != 0;
       const double vm = mine ? vol : inner ? g.vol[nb] : vol;

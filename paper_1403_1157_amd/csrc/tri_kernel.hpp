@@ -70,10 +70,20 @@ struct TriSz {
   static constexpr int NFQ = 14;   // edge slots as in the Cartesian kernel
 };
 
+// Per-element strides of the exchange slots, odd in doubles: with an even stride
+// that is a multiple of 16 doubles (P1 and P3 volume slots) every element of a
+// species hits the same LDS bank, a 32-way conflict; odd strides spread the 32
+// elements over all banks.
+template <int K>
+struct TriStride {
+  using S = TriSz<K>;
+  static constexpr int VS = S::NVQ * S::NQ + 1, FS = S::NFQ * S::NE + 1;
+};
+
 template <int K>
 struct TriSmem {
   using S = TriSz<K>;
-  static constexpr int VOL = TRI_EB * S::NVQ * S::NQ, FAC = TRI_EB * S::NFQ * S::NE;
+  static constexpr int VOL = TRI_EB * TriStride<K>::VS, FAC = TRI_EB * TriStride<K>::FS;
   static constexpr int N = VOL > FAC ? VOL : FAC;
   double buf[N];
   double etab[3 * S::NE * S::NB * 3];   // edge tables: [edge][point][mode][value, d/dxi, d/deta]
@@ -88,7 +98,8 @@ __global__ void __launch_bounds__(6 * TRI_EB, K == 3 ? 2 : 3)
 tri_kernel(const TriParams* __restrict__ prm, const double* __restrict__ U, const double* U0, double* out,
            double dt, double ca, double cb, int stage, int* __restrict__ flags) {
   using S = TriSz<K>;
-  constexpr int NB = S::NB, NQ = S::NQ, NE = S::NE, NVQ = S::NVQ, NT = 6 * TRI_EB;
+  constexpr int NB = S::NB, NQ = S::NQ, NE = S::NE, NT = 6 * TRI_EB;
+  constexpr int VS = TriStride<K>::VS, FS = TriStride<K>::FS;
   __shared__ TriSmem<K> sm;
   const TriTables& tb = prm->tb;
   const TriGeo& g = prm->g;
@@ -123,12 +134,12 @@ tri_kernel(const TriParams* __restrict__ prm, const double* __restrict__ U, cons
   const double as = c[K_MU1 + s];
 
   // ---- volume ---------------------------------------------------------------------
-  double* V = sm.buf;   // [EB][NVQ][NQ]
+  double* V = sm.buf;   // [EB][VS]: NVQ slots of NQ points, then one pad
   const int vslot = s == S_N1 ? 0 : s == S_N2 ? 1 : s == S_C1 ? 2 : s == S_C3 ? 3 : s == S_N3 ? 10 : 11;
   const int gslot = s == S_N1 ? 4 : s == S_C1 ? 6 : s == S_C3 ? 8 : -1;
   double gq[NQ][2];
   {
-    double* o = V + el * NVQ * NQ;
+    double* o = V + el * VS;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       double v = 0.0, r0 = 0.0, r1 = 0.0;
@@ -151,7 +162,7 @@ tri_kernel(const TriParams* __restrict__ prm, const double* __restrict__ U, cons
   // point items: chemotactic fluxes F1 (slots 4, 5), F2 (6, 7), alpha term (8)
   for (int it = tid; it < TRI_EB * NQ; it += NT) {
     const int l = it / NQ, q = it % NQ;
-    double* x = V + l * NVQ * NQ + q;
+    double* x = V + l * VS + q;
     const double n1 = x[0], n2 = x[NQ], c1 = x[2 * NQ], c3 = x[3 * NQ];
     const double d11 = c1 + c[K_XT11], d13 = c3 + c[K_XT13], d21 = c1 + c[K_XT21], d22 = n1 + c[K_XT22];
     if (e0 + l < E && !(d11 > 0.0 && d13 > 0.0 && d21 > 0.0 && d22 > 0.0)) flag |= FLAG_DOMAIN;
@@ -182,7 +193,7 @@ tri_kernel(const TriParams* __restrict__ prm, const double* __restrict__ U, cons
     const double k1 = s == S_N3 ? c[K_D2] : 0.0;
     const int fs = s == S_N2 ? 6 : 4;
     const double fw = s == S_N1 || s == S_N2 ? 1.0 : 0.0, rw = s == S_C1 ? 1.0 : 0.0;
-    const double* x = V + el * NVQ * NQ;
+    const double* x = V + el * VS;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const double wt = area * tb.wv[q];
@@ -197,7 +208,7 @@ tri_kernel(const TriParams* __restrict__ prm, const double* __restrict__ U, cons
   }
 
   // ---- edges ----------------------------------------------------------------------
-  double* Fx = sm.buf;   // [EB][NFQ][NE]
+  double* Fx = sm.buf;   // [EB][FS]: NFQ slots of NE points, then one pad
   const int fvslot = s == S_N1 ? 0 : s == S_N2 ? 1 : s == S_C1 ? 2 : s == S_C3 ? 3 : -1;
   const int dslot = s == S_N1 ? 8 : s == S_C1 ? 9 : s == S_C3 ? 10 : -1;
 #pragma unroll 1
@@ -246,22 +257,22 @@ tri_kernel(const TriParams* __restrict__ prm, const double* __restrict__ U, cons
     if (fvslot >= 0) {
 #pragma unroll
       for (int p = 0; p < NE; ++p) {
-        Fx[(el * 14 + fvslot) * NE + p] = uo[p];
-        Fx[(el * 14 + 4 + fvslot) * NE + p] = un[p];
+        Fx[el * FS + fvslot * NE + p] = uo[p];
+        Fx[el * FS + (4 + fvslot) * NE + p] = un[p];
       }
     }
     if (dslot >= 0) {
 #pragma unroll
       for (int p = 0; p < NE; ++p) {
-        Fx[(el * 14 + dslot) * NE + p] = dno[p];
-        Fx[(el * 14 + dslot + 3) * NE + p] = dnn[p];
+        Fx[el * FS + dslot * NE + p] = dno[p];
+        Fx[el * FS + (dslot + 3) * NE + p] = dnn[p];
       }
     }
     __syncthreads();
     // edge point items: lambda / 2, -(F1 + F1').n / 2, -(F2 + F2').n / 2, or inflow
     for (int it = tid; it < TRI_EB * NE; it += NT) {
       const int l = it / NE, p = it % NE;
-      double* x = Fx + l * 14 * NE + p;
+      double* x = Fx + l * FS + p;
       const int el2 = e0 + l;
       const int nbl = el2 < E ? g.nbr[3 * el2 + k] : -3;
       const double c1o = x[2 * NE];
@@ -307,7 +318,7 @@ tri_kernel(const TriParams* __restrict__ prm, const double* __restrict__ U, cons
     __syncthreads();
     // species pass
     if (live) {
-      const double* x = Fx + el * 14 * NE;
+      const double* x = Fx + el * FS;
       const double len = g.len[3 * e + k];
       double G[NE], H[NE];
       if (nb >= 0) {
