@@ -89,27 +89,27 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
   }
 
   // ---- linear diffusion (symmetric: applied to v), parameter derivative via a = 1 -----
+  // d/d a_s of the diffusion part is the a_s = 1 form of u against v; it is
+  // accumulated as the scalar thd term by term (volume here, faces below) rather
+  // than through a second residual array, which would not fit the registers at
+  // 3D p = 3.  The form is symmetric, so the volume part is S(v) . u.
   const T as = T(c[K_MU1 + s]);
-  T Ru[NM];   // diffusion residual of u with a_s = 1 (for d/d a_s), only if requested
+  double thd = 0.0;
 #pragma unroll
   for (int m = 0; m < NM; ++m) {
-    T accv = T(0), accu = T(0);
+    T accv = T(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       const int st = ipow(Q, a);
       const int ia = (m / st) % Q;
       const int base = m - ia * st;
-      T sv = T(0), su = T(0);
+      T sv = T(0);
 #pragma unroll
-      for (int j = 0; j < Q; ++j) {
-        sv += T(tb.S[ia][j]) * v[base + j * st];
-        su += T(tb.S[ia][j]) * u[base + j * st];
-      }
+      for (int j = 0; j < Q; ++j) sv += T(tb.S[ia][j]) * v[base + j * st];
       accv += T(g.ih[a] * g.ih[a]) * sv;
-      accu += T(g.ih[a] * g.ih[a]) * su;
     }
     R[m] = -as * vol * accv;
-    Ru[m] = -vol * accu;
+    if (want_theta) thd += (double)(-vol * accv) * (double)u[m];
   }
   // transposed linear reactions: (J^T w)_{s'} += sum_s L[s][s'] w_s = vol sum_s L[s][s'] v_s
   {
@@ -346,77 +346,121 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
     const int f = 2 * a + sg;
     __syncthreads();
     const int nb = sm.nb[el][f];
-    T uo[NF], duo[NF], un[NF], dun[NF], jm[NF];
-    T vo[NF], dvo[NF], vn[NF], dvn[NF], jv[NF];
-#pragma unroll
-    for (int J = 0; J < NF; ++J) {
-      T a0 = T(0), a1 = T(0), b0 = T(0), b1 = T(0);
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const int m = face_mode<D, Q>(a, i, J);
-        a0 += T(tb.E[sg][i]) * u[m];
-        a1 += T(tb.dE[sg][i]) * u[m];
-        b0 += T(tb.E[sg][i]) * v[m];
-        b1 += T(tb.dE[sg][i]) * v[m];
-      }
-      uo[J] = a0;
-      duo[J] = a1 * T(g.ih[a]);
-      vo[J] = b0;
-      dvo[J] = b1 * T(g.ih[a]);
-      un[J] = dun[J] = jm[J] = vn[J] = dvn[J] = jv[J] = T(0);
-    }
-    if (nb >= 0) {
-      const T* us = U + s * SE + (size_t)nb * NM;
-      const T* ws = W + s * SE + (size_t)nb * NM;
+    const double(*Tb0)[CDG2_MAXQ] = tb.B;
+    // The traces are formed and published one group at a time, and only what the
+    // species pass needs is kept: the normal-derivative averages and the jumps
+    // of u and of v.  At 3D p = 3 a scheduling fence separates the groups (all
+    // ten trace arrays at once did not fit the registers); elsewhere the
+    // compiler may interleave them, which measured faster.
+    constexpr bool FENCE = D == 3 && P == 3;
+    T sdu[NF], jm[NF], sdv[NF], jv[NF];
+    const bool inner = nb >= 0;
+    const T* us = U + s * SE + (size_t)(inner ? nb : (live ? e : 0)) * NM;   // in range; unused on boundaries
+    const T* ws = W + s * SE + (size_t)(inner ? nb : (live ? e : 0)) * NM;
+    // trace of the modes x at end `side` along axis a (d: derivative, scaled by 1/h_a)
+    auto own_tr = [&](const T* x, int side, bool d, T* o) {
 #pragma unroll
       for (int J = 0; J < NF; ++J) {
-        T a0 = T(0), a1 = T(0), a2 = T(0), b0 = T(0), b1 = T(0), b2 = T(0);
+        T acc = T(0);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          const int m = face_mode<D, Q>(a, i, J);
-          const T x0 = us[m], y0 = ws[m] * ivol;
-          a0 += T(tb.E[1 - sg][i]) * x0;
-          a1 += T(tb.dE[1 - sg][i]) * x0;
-          a2 += i == 0 ? u[m] - x0 : T(tb.E[sg][i]) * u[m] - T(tb.E[1 - sg][i]) * x0;
-          b0 += T(tb.E[1 - sg][i]) * y0;
-          b1 += T(tb.dE[1 - sg][i]) * y0;
-          b2 += i == 0 ? v[m] - y0 : T(tb.E[sg][i]) * v[m] - T(tb.E[1 - sg][i]) * y0;
+        for (int i = 0; i < Q; ++i) acc += T(d ? tb.dE[side][i] : tb.E[side][i]) * x[face_mode<D, Q>(a, i, J)];
+        o[J] = d ? acc * T(g.ih[a]) : acc;
+      }
+    };
+    auto nb_tr = [&](const T* src, T scale, bool d, T* o) {
+#pragma unroll
+      for (int J = 0; J < NF; ++J) {
+        T acc = T(0);
+        if (inner) {
+#pragma unroll
+          for (int i = 0; i < Q; ++i)
+            acc += T(d ? tb.dE[1 - sg][i] : tb.E[1 - sg][i]) * (src[face_mode<D, Q>(a, i, J)] * scale);
         }
-        un[J] = a0;
-        dun[J] = a1 * T(g.ih[a]);
-        jm[J] = a2;
-        vn[J] = b0;
-        dvn[J] = b1 * T(g.ih[a]);
-        jv[J] = b2;
+        o[J] = d ? acc * T(g.ih[a]) : acc;
+      }
+    };
+    // jump own - neighbour of modes x (own, registers) and src (neighbour), with
+    // the mean terms differenced first
+    auto jump = [&](const T* x, const T* src, T scale, T* o) {
+#pragma unroll
+      for (int J = 0; J < NF; ++J) {
+        T acc = T(0);
+        if (inner) {
+#pragma unroll
+          for (int i = 0; i < Q; ++i) {
+            const int m = face_mode<D, Q>(a, i, J);
+            const T y = src[m] * scale;
+            acc += i == 0 ? x[m] - y : T(tb.E[sg][i]) * x[m] - T(tb.E[1 - sg][i]) * y;
+          }
+        }
+        o[J] = acc;
+      }
+    };
+    // the neighbour's modes: read where they are used at 3D p = 3, else loaded
+    // once into registers (three reads per face measured slower there)
+    T nbu[FENCE ? 1 : NM], nbw[FENCE ? 1 : NM];
+    if constexpr (!FENCE) {
+#pragma unroll
+      for (int m = 0; m < NM; ++m) {
+        nbu[m] = us[m];
+        nbw[m] = ws[m];
       }
     }
-    const double(*Tb0)[CDG2_MAXQ] = tb.B;
+    const T* su = FENCE ? us : nbu;
+    const T* sw = FENCE ? ws : nbw;
     {
       T o[NF];
       if (vslot >= 0) {
-        tapply_lo<D, Q, false, T>(uo, o, Tb0, Tb0);
+        T tr[NF];
+        own_tr(u, sg, false, tr);
+        tapply_lo<D, Q, false, T>(tr, o, Tb0, Tb0);
 #pragma unroll
         for (int t = 0; t < NF; ++t) Fx[(el * 26 + vslot) * NF + t] = o[t];
-        tapply_lo<D, Q, false, T>(un, o, Tb0, Tb0);
+        nb_tr(su, T(1), false, tr);
+        tapply_lo<D, Q, false, T>(tr, o, Tb0, Tb0);
 #pragma unroll
         for (int t = 0; t < NF; ++t) Fx[(el * 26 + 4 + vslot) * NF + t] = o[t];
       }
-      if (dslot >= 0) {
-        tapply_lo<D, Q, false, T>(duo, o, Tb0, Tb0);
+      if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
+      {
+        T d0[NF], d1[NF];
+        own_tr(u, sg, true, d0);
+        nb_tr(su, T(1), true, d1);
+        if (dslot >= 0) {
+          tapply_lo<D, Q, false, T>(d0, o, Tb0, Tb0);
 #pragma unroll
-        for (int t = 0; t < NF; ++t) Fx[(el * 26 + dslot) * NF + t] = o[t];
-        tapply_lo<D, Q, false, T>(dun, o, Tb0, Tb0);
+          for (int t = 0; t < NF; ++t) Fx[(el * 26 + dslot) * NF + t] = o[t];
+          tapply_lo<D, Q, false, T>(d1, o, Tb0, Tb0);
 #pragma unroll
-        for (int t = 0; t < NF; ++t) Fx[(el * 26 + dslot + 3) * NF + t] = o[t];
+          for (int t = 0; t < NF; ++t) Fx[(el * 26 + dslot + 3) * NF + t] = o[t];
+        }
+#pragma unroll
+        for (int J = 0; J < NF; ++J) sdu[J] = d0[J] + d1[J];
       }
-      // adjoint jump psi_own - psi_nb and forward jump at the points (boundary:
-      // psi_own, 0)
-      tapply_lo<D, Q, false, T>(nb >= 0 ? jv : vo, o, Tb0, Tb0);
-#pragma unroll
-      for (int t = 0; t < NF; ++t) Fx[(el * 26 + 14 + s) * NF + t] = o[t];
+      if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
+      // forward jump at the points (boundary: 0)
+      jump(u, su, T(1), jm);
       tapply_lo<D, Q, false, T>(jm, o, Tb0, Tb0);
 #pragma unroll
       for (int t = 0; t < NF; ++t) Fx[(el * 26 + 20 + s) * NF + t] = o[t];
+      if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
+      {
+        T d0[NF], d1[NF];
+        own_tr(v, sg, true, d0);
+        nb_tr(sw, ivol, true, d1);
+#pragma unroll
+        for (int J = 0; J < NF; ++J) sdv[J] = d0[J] + d1[J];
+      }
+      if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
+      // adjoint jump psi_own - psi_nb (boundary: psi_own)
+      if (inner) {
+        jump(v, sw, ivol, jv);
+      } else {
+        own_tr(v, sg, false, jv);
+      }
+      tapply_lo<D, Q, false, T>(jv, o, Tb0, Tb0);
+#pragma unroll
+      for (int t = 0; t < NF; ++t) Fx[(el * 26 + 14 + s) * NF + t] = o[t];
     }
     __syncthreads();
     // face point pass: derivatives of sum_s g_s dpsi_s with respect to the own
@@ -546,9 +590,9 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
       for (int J = 0; J < NF; ++J) {
         T lin = T(0), hh = T(0), linu = T(0), hhu = T(0);
         if (nb >= 0) {
-          lin = as * (so * T(0.5) * (dvo[J] + dvn[J]) - pen * jv[J]);
+          lin = as * (so * T(0.5) * sdv[J] - pen * jv[J]);
           hh = as * T(0.5) * jv[J] * so * T(g.ih[a]);
-          linu = so * T(0.5) * (duo[J] + dun[J]) - pen * jm[J];
+          linu = so * T(0.5) * sdu[J] - pen * jm[J];
           hhu = T(0.5) * jm[J] * so * T(g.ih[a]);
         }
         G[J] = ar * (lin + gh[J]);
@@ -562,7 +606,8 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
         for (int J = 0; J < NF; ++J) {
           const int m = face_mode<D, Q>(a, i, J);
           R[m] += T(tb.E[sg][i]) * G[J] + T(tb.dE[sg][i]) * H[J];
-          Ru[m] += T(tb.E[sg][i]) * Gu[J] + T(tb.dE[sg][i]) * Hu[J];
+          if (want_theta)
+            thd += (double)(T(tb.E[sg][i]) * Gu[J] + T(tb.dE[sg][i]) * Hu[J]) * (double)v[m];
         }
     }
   }
@@ -580,12 +625,7 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
       out[off + m] = val;
     }
   }
-  // d/d a_s of the diffusion part: the a_s = 1 residual of u against v
-  double thd = 0.0;
-  if (want_theta && live) {
-#pragma unroll
-    for (int m = 0; m < NM; ++m) thd += (double)Ru[m] * (double)v[m];
-  }
+  if (!live) thd = 0.0;
   if (flag) atomicOr(flags, flag);
 
   // ---- deterministic per-workgroup reduction of the parameter derivatives -----------
