@@ -17,9 +17,10 @@ the residual <phi_j, L_h(U)> of the six-species model of Section 2 with
     so phi_0 = 1 (mode 0 is the element mean) and M_K = |K| I;
   * volume integrals with a fully symmetric rule on the tetrahedron exact for
     degree 2k (the mass matrix): k = 1: 4 points, degree 2; k = 2: 14 points,
-    degree 4; k = 3: 24 points, degree 6; orbits of the vertex permutations
-    with positive weights, their parameters solving the moment equations
-    (Newton, here);
+    degree 5 (at degree 4 that layout is a one-parameter family of rules;
+    degree 5 leaves one); k = 3: 24 points, degree 6; orbits of the vertex
+    permutations with positive weights, their parameters solving the moment
+    equations (Newton, here);
   * face integrals with a fully symmetric rule on the triangle, exact for
     degree 2k (k = 1: 3 points, degree 2; k = 2: 6 points, degree 4; k = 3:
     12 points, degree 6), so that both elements of a face use the same physical
