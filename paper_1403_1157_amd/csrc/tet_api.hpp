@@ -449,16 +449,16 @@ void tet_free(cdg2_tet* t) {
 
 hipError_t tet_launch(cdg2_tet* t, const double* U, const double* U0, double* out, double dt, double ca, double cb,
                       int stage) {
-  const int nblk = (t->E + TET_EB - 1) / TET_EB;
+  auto nblk = [&](int eb) { return (t->E + eb - 1) / eb; };
   if (t->k == 1)
-    hipLaunchKernelGGL((tet_kernel<1>), dim3(nblk), dim3(6 * TET_EB), 0, t->stream, t->dprm, U, U0, out, dt, ca, cb,
-                       stage, t->flags);
+    hipLaunchKernelGGL((tet_kernel<1>), dim3(nblk(tet_eb<1>())), dim3(6 * tet_eb<1>()), 0, t->stream, t->dprm, U, U0,
+                       out, dt, ca, cb, stage, t->flags);
   else if (t->k == 2)
-    hipLaunchKernelGGL((tet_kernel<2>), dim3(nblk), dim3(6 * TET_EB), 0, t->stream, t->dprm, U, U0, out, dt, ca, cb,
-                       stage, t->flags);
+    hipLaunchKernelGGL((tet_kernel<2>), dim3(nblk(tet_eb<2>())), dim3(6 * tet_eb<2>()), 0, t->stream, t->dprm, U, U0,
+                       out, dt, ca, cb, stage, t->flags);
   else
-    hipLaunchKernelGGL((tet_kernel<3>), dim3(nblk), dim3(6 * TET_EB), 0, t->stream, t->dprm, U, U0, out, dt, ca, cb,
-                       stage, t->flags);
+    hipLaunchKernelGGL((tet_kernel<3>), dim3(nblk(tet_eb<3>())), dim3(6 * tet_eb<3>()), 0, t->stream, t->dprm, U, U0,
+                       out, dt, ca, cb, stage, t->flags);
   return hipGetLastError();
 }
 

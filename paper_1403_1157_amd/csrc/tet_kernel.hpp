@@ -17,7 +17,7 @@
 // on Gamma1 / Gamma2 the inflow fluxes of eqs. (7)-(9).  Then f = R / |K|,
 // optionally combined with an SSP-RK3 stage in the epilogue.
 //
-// Mapping: a workgroup owns TET_EB elements; thread (s, el) keeps the modes and
+// Mapping: a workgroup owns tet_eb<K>() elements; thread (s, el) keeps the modes and
 // the residual of species s of element el in registers.  The nonlinear terms go
 // through LDS: the volume points in chunks of TetSz::QC, then the faces one
 // local face index at a time (all its points at once).  The neighbour's local
@@ -35,7 +35,10 @@ namespace cdg2 {
 constexpr int TET_MAXB = 20;   // P_3
 constexpr int TET_MAXQ = 24;   // points of the symmetric volume rule (degree 2k)
 constexpr int TET_MAXF = 12;   // points of the symmetric face rule (degree 2k)
-constexpr int TET_EB = 32;     // elements per workgroup (192 threads)
+// Elements per workgroup (6 threads each): 32, and 20 for P3, whose face table
+// then fits in LDS beside the exchange slots (two workgroups per CU).
+template <int K>
+constexpr int tet_eb() { return K == 3 ? 20 : 32; }
 
 // Reference tables (host-built).
 struct TetTables {
@@ -84,11 +87,12 @@ struct TetSz {
   static constexpr int NFQ = 14;   // face slots as in the other kernels
 };
 
-// The interleaved face table goes to LDS for P1 and P2 (1.5 KB and 7.7 KB); the
-// 30 KB of P3 are read through the cache instead, which leaves LDS for two
-// workgroups per CU.
+// The interleaved face table goes to LDS (1.5, 7.7 and 30 KB for P1, P2, P3):
+// the neighbour's local face and orientation differ from lane to lane, and read
+// through the cache the P3 table kept the vector-memory return path busy (each
+// lane reads the whole table once per application).
 template <int K>
-constexpr bool tet_ftab_in_lds() { return K <= 2; }
+constexpr bool tet_ftab_in_lds() { return true; }
 
 // Per-element (and per-thread) strides of the LDS slots, odd in doubles: the
 // plain strides (15 QC, 14 NF, 2 NF doubles) put the 32 elements of a species on
@@ -102,19 +106,20 @@ struct TetStride {
 template <int K>
 struct TetSmem {
   using S = TetSz<K>;
-  static constexpr int VOL = TET_EB * TetStride<K>::VS, FAC = TET_EB * TetStride<K>::FS;
+  static constexpr int VOL = tet_eb<K>() * TetStride<K>::VS, FAC = tet_eb<K>() * TetStride<K>::FS;
   static constexpr int N = VOL > FAC ? VOL : FAC;
   double buf[N];
-  double park[6 * TET_EB * TetStride<K>::PS];   // each thread's face jump and normal-derivative sum
+  double park[6 * tet_eb<K>() * TetStride<K>::PS];   // each thread's face jump and normal-derivative sum
   double ftab[tet_ftab_in_lds<K>() ? 4 * S::NF * S::NB * 4 : 1];   // [face][point][mode][4]
 };
 
 // Two waves per SIMD (the registers of P2 and P3 and the LDS of P3 allow no more).
 template <int K>
-__global__ void __launch_bounds__(6 * TET_EB, 2)
+__global__ void __launch_bounds__(6 * tet_eb<K>(), 2)
 tet_kernel(const TetParams* __restrict__ prm, const double* __restrict__ U, const double* U0, double* out,
            double dt, double ca, double cb, int stage, int* __restrict__ flags) {
   using S = TetSz<K>;
+  constexpr int TET_EB = tet_eb<K>();
   constexpr int NB = S::NB, NQ = S::NQ, NF = S::NF, QC = S::QC, NT = 6 * TET_EB;
   constexpr int VS = TetStride<K>::VS, FS = TetStride<K>::FS, PS = TetStride<K>::PS;
   __shared__ TetSmem<K> sm;
