@@ -60,11 +60,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_profile(workload: str):
-    """HBM traffic and counted FP64 flops per step from the committed rocprofv3
-    --pmc summary of this workload, if it was taken on the current kernel
-    sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"op_kernel_{workload}_pmc.txt")
+def read_pmc(name: str):
+    """The key = value lines of the committed rocprofv3 --pmc summary
+    profiles/<name>_pmc.txt, if it was taken on the current kernel sources; else
+    None."""
+    path = os.path.join(ROOT, "profiles", f"{name}_pmc.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -74,10 +74,29 @@ def read_profile(workload: str):
             kv[k.strip()] = v.strip()
     if kv.get("source_hash") != kernel_source_hash():
         return None
+    return kv
+
+
+def read_profile(workload: str):
+    """HBM traffic and counted FP64 flops per step of a Cartesian workload."""
+    kv = read_pmc(f"op_kernel_{workload}")
     try:
         return {"bytes_per_step": float(kv["bytes_per_step"]), "flops_per_step": float(kv["flops_per_step"])}
-    except (KeyError, ValueError):
+    except (KeyError, TypeError, ValueError):
         return None
+
+
+def fp64_of_apply(name: str, k: int, us_apply: float):
+    """FP64 rate of one operator application of order k on a simplex mesh, from
+    the counted flops per application in profiles/<name>_pmc.txt (None if the
+    profile is missing or was taken on other kernel sources)."""
+    kv = read_pmc(name)
+    try:
+        fl = float(kv[f"flops_apply_p{k}"])
+    except (KeyError, TypeError, ValueError):
+        return None
+    tf = fl / (us_apply * 1e-6) / 1e12
+    return {"flop_per_apply": fl, "tflop_s": round(tf, 3), "frac": round(tf / FP64_PEAK_TFS, 4)}
 
 
 def host_cpu_model() -> str:
@@ -350,7 +369,8 @@ def bench_triangles(n=256, steps=100, reps=200):
     """Unstructured P_k triangles: an n x n Kuhn mesh of [0,1]^2 with jittered
     vertices (2 n^2 triangles), P1, P2 and P3; operator applications and an SSP-RK3
     run.  Algorithmic bytes as for the Cartesian grids (16 B/DOF per apply,
-    64 B/DOF per step, state only)."""
+    64 B/DOF per step, state only); the FP64 rate of an application from the
+    counted flops of the committed profile (the kernels are arithmetic-bound)."""
     import torch
 
     from paper_1403_1157_amd import inputs
@@ -373,6 +393,7 @@ def bench_triangles(n=256, steps=100, reps=200):
         us_step = 1e3 * time_ms(lambda: op.rk_step(U, 2e-8, steps)) / steps
         op.sync()
         out[f"p{k}"] = {"us_per_apply": round(us_apply, 2), "apply_frac": round(16 * dof / us_apply / 1e3 / HBM_PEAK_GBS, 4),
+                        "apply_fp64": fp64_of_apply("tri_kernel_kuhn-256", k, us_apply),
                         "us_per_step": round(us_step, 2), "step_frac": round(64 * dof / us_step / 1e3 / HBM_PEAK_GBS, 4),
                         "gdof_s": round(3 * dof / us_step / 1e3, 3)}
     return {"workload": f"{n}x{n} Kuhn mesh, jittered ({2 * n * n} triangles), {reps} applies and a "
@@ -406,6 +427,7 @@ def bench_tetrahedra(n=(26, 26, 28), steps=20, reps=50):
         us_step = 1e3 * time_ms(lambda: op.rk_step(U, 1e-8, steps)) / steps
         op.sync()
         out[f"p{k}"] = {"dof": dof, "us_per_apply": round(us_apply, 2),
+                        "apply_fp64": fp64_of_apply("tet_kernel_kuhn-26", k, us_apply),
                         "apply_frac": round(16 * dof / us_apply / 1e3 / HBM_PEAK_GBS, 4),
                         "us_per_step": round(us_step, 2), "step_frac": round(64 * dof / us_step / 1e3 / HBM_PEAK_GBS, 4),
                         "gdof_s": round(3 * dof / us_step / 1e3, 3)}

@@ -1,10 +1,11 @@
-// Batched persistent SSP-RK3 stage kernel: many independent 2D instances with
-// different grids, orders and coefficient sets in one launch per stage.
+// Batched SSP-RK3 stage kernel: many independent 2D instances with different
+// grids, orders and coefficient sets in one launch per stage (or one per order).
 //
 // The work list holds one item per (instance, block of EB cells), sorted by the
-// host (by default by decreasing cost).  A fixed grid of workgroups walks it with
-// a static stride (item = blockIdx.x + k * gridDim.x), so the launch is
-// persistent without a dynamic queue and the schedule is reproducible.  Each item
+// host (by default by decreasing cost).  The grid is either one workgroup per
+// item, or a fixed number of persistent workgroups that walk the list with a
+// static stride (item = blockIdx.x + k * gridDim.x: no dynamic queue, so the
+// schedule is reproducible); the autotuner picks.  Each item
 // runs the same per-block code as the single-instance kernel (es_block), chosen
 // by the instance's order p (uniform within a workgroup), on the LDS buffer sized
 // for the largest order.

@@ -35,10 +35,10 @@ namespace cdg2 {
 constexpr int TET_MAXB = 20;   // P_3
 constexpr int TET_MAXQ = 24;   // points of the symmetric volume rule (degree 2k)
 constexpr int TET_MAXF = 12;   // points of the symmetric face rule (degree 2k)
-// Elements per workgroup (6 threads each): 32, and 20 for P3, whose face table
+// Elements per workgroup (6 threads each): 32, and 19 for P3, whose face table
 // then fits in LDS beside the exchange slots (two workgroups per CU).
 template <int K>
-constexpr int tet_eb() { return K == 3 ? 20 : 32; }
+constexpr int tet_eb() { return K == 3 ? 19 : 32; }
 
 // Reference tables (host-built).
 struct TetTables {
@@ -87,12 +87,15 @@ struct TetSz {
   static constexpr int NFQ = 14;   // face slots as in the other kernels
 };
 
-// The interleaved face table goes to LDS (1.5, 7.7 and 30 KB for P1, P2, P3):
+// The interleaved face table lives in LDS (1.7, 7.9 and 30.8 KB for P1, P2, P3):
 // the neighbour's local face and orientation differ from lane to lane, and read
 // through the cache the P3 table kept the vector-memory return path busy (each
-// lane reads the whole table once per application).
+// lane reads the whole table once per application).  Each (face, point) row of
+// NB x 4 values is padded by two doubles: unpadded, the rows of P3 (160 dwords)
+// and P2 (80) start on one or two LDS banks, and lanes reading the same mode of
+// different rows collide (a 4.5-fold conflict measured at P3).
 template <int K>
-constexpr bool tet_ftab_in_lds() { return true; }
+constexpr int tet_frow() { return TetSz<K>::NB * 4 + 2; }
 
 // Per-element (and per-thread) strides of the LDS slots, odd in doubles: the
 // plain strides (15 QC, 14 NF, 2 NF doubles) put the 32 elements of a species on
@@ -110,7 +113,7 @@ struct TetSmem {
   static constexpr int N = VOL > FAC ? VOL : FAC;
   double buf[N];
   double park[6 * tet_eb<K>() * TetStride<K>::PS];   // each thread's face jump and normal-derivative sum
-  double ftab[tet_ftab_in_lds<K>() ? 4 * S::NF * S::NB * 4 : 1];   // [face][point][mode][4]
+  double ftab[4 * S::NF * tet_frow<K>()];   // [face][point] rows of [mode][4], padded
 };
 
 // Two waves per SIMD (the registers of P2 and P3 and the LDS of P3 allow no more).
@@ -144,11 +147,10 @@ tet_kernel(const TetParams* __restrict__ prm, const double* __restrict__ U, cons
       R[j] = 0.0;
     }
   }
-  if constexpr (tet_ftab_in_lds<K>()) {
-    for (int i = tid; i < 4 * NF * NB * 4; i += NT) {
-      const int c4 = i % 4, j = (i / 4) % NB, p = (i / (4 * NB)) % NF, f = i / (4 * NB * NF);
-      sm.ftab[i] = tb.ftab[f][p][j][c4];
-    }
+  constexpr int FR = tet_frow<K>();
+  for (int i = tid; i < 4 * NF * NB * 4; i += NT) {
+    const int c4 = i % 4, j = (i / 4) % NB, p = (i / (4 * NB)) % NF, f = i / (4 * NB * NF);
+    sm.ftab[(f * NF + p) * FR + 4 * j + c4] = tb.ftab[f][p][j][c4];
   }
   double jt[9];
 #pragma unroll
@@ -251,11 +253,7 @@ tet_kernel(const TetParams* __restrict__ prm, const double* __restrict__ U, cons
 
   // ---- faces ----------------------------------------------------------------------
   double* Fx = sm.buf;   // [EB][FS]: NFQ slots of NF points, then one pad
-  const double* ft;
-  if constexpr (tet_ftab_in_lds<K>())
-    ft = sm.ftab;
-  else
-    ft = &tb.ftab[0][0][0][0];
+  const double* ft = sm.ftab;
   double* park = sm.park + tid * PS;
   const int fvslot = s == S_N1 ? 0 : s == S_N2 ? 1 : s == S_C1 ? 2 : s == S_C3 ? 3 : -1;
   const int dslot = s == S_N1 ? 8 : s == S_C1 ? 9 : s == S_C3 ? 10 : -1;
@@ -295,7 +293,7 @@ tet_kernel(const TetParams* __restrict__ prm, const double* __restrict__ U, cons
         a2 += tb.Bgf[f][p][j][2] * u[j];
       }
       const double uo = v, dno = dw0 * a0 + dw1 * a1 + dw2 * a2;
-      const double* t = ft + (gf * NF + tb.perm[ori][p]) * NB * 4;
+      const double* t = ft + (gf * NF + tb.perm[ori][p]) * FR;
       double vn = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
@@ -382,7 +380,7 @@ tet_kernel(const TetParams* __restrict__ prm, const double* __restrict__ U, cons
 #pragma unroll 1
         for (int p = 0; p < NF; ++p) {
           const double gm = sgn * park[p] * (ar * tb.wf[p]);
-          const double* t = mine ? ft + (f * NF + p) * NB * 4 : ft + (gf * NF + tb.perm[ori][p]) * NB * 4;
+          const double* t = mine ? ft + (f * NF + p) * FR : ft + (gf * NF + tb.perm[ori][p]) * FR;
 #pragma unroll
           for (int j = 0; j < NB; ++j) proj[j] += gm * t[4 * j];
         }
@@ -395,7 +393,7 @@ tet_kernel(const TetParams* __restrict__ prm, const double* __restrict__ U, cons
       const double kw = inner ? (s == S_N1 || s == S_N2 ? 1.0 : 0.0) : (s == S_N1 || s == S_N2 || s == S_C2 ? 1.0 : 0.0);
 #pragma unroll 1
       for (int p = 0; p < NF; ++p) {
-        const double* t = mine ? ft + (f * NF + p) * NB * 4 : ft + (gf * NF + tb.perm[ori][p]) * NB * 4;
+        const double* t = mine ? ft + (f * NF + p) * FR : ft + (gf * NF + tb.perm[ori][p]) * FR;
         const double jm = park[p], sd = park[NF + p];
         double rt = 0.0;
 #pragma unroll
