@@ -577,6 +577,13 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
 #pragma unroll
       for (int t = 0; t < NF; ++t) Fx[(el * 14 + dslot + 3) * NF + t] = o[t];
     }
+    // the species pass needs only the weighted derivative sum (own is K^- on the
+    // high face, sg = 1) and the jump: formed now, so that the four trace arrays
+    // are not live through the point pass
+    const T wo = T(sg ? g.wm : g.wp), wn = T(sg ? g.wp : g.wm);
+    T sd[NF];
+#pragma unroll
+    for (int J = 0; J < NF; ++J) sd[J] = wo * duo[J] + wn * dun[J];
     __syncthreads();
     // face point pass
     for (int it = tid; it < EB * NF; it += NT) {
@@ -661,14 +668,11 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
       const T so = sg ? T(1) : T(-1);
       const T pen = T(g.pen_c * tb.liftc * g.ih[a]) * as;
       T G[NF], H[NF];
-      // weights of the own side and the neighbour in the average (own is K^- on the
-      // high face, sg = 1)
-      const T wo = T(sg ? g.wm : g.wp), wn = T(sg ? g.wp : g.wm);
 #pragma unroll
       for (int J = 0; J < NF; ++J) {
         T lin = T(0), hh = T(0);
         if (nb >= 0) {
-          lin = so * as * (wo * duo[J] + wn * dun[J]) - pen * jm[J];
+          lin = so * as * sd[J] - pen * jm[J];
           hh = wo * T(g.sym) * as * jm[J] * so * T(g.ih[a]);
         }
         G[J] = ar * (lin + gh[J]);
