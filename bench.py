@@ -100,15 +100,25 @@ def fp64_of_apply(name: str, k: int, us_apply: float):
 
 
 def host_cpu_model() -> str:
-    """Model name of the host CPU (from /proc/cpuinfo, as lscpu reports it)."""
+    """Model name of the host CPU (from /proc/cpuinfo, as lscpu reports it), with
+    the CPU family, model and stepping numbers (a virtual machine may report only
+    a generic name)."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if ":" in line:
+                    k, v = line.split(":", 1)
+                    k = k.strip()
+                    if k in ("model name", "cpu family", "model", "stepping") and k not in info:
+                        info[k] = v.strip()
+                if not line.strip() and info:
+                    break
     except OSError:
         pass
-    return "unknown"
+    name = info.get("model name", "unknown")
+    nums = ", ".join(f"{k} {info[k]}" for k in ("cpu family", "model", "stepping") if k in info)
+    return f"{name} ({nums})" if nums else name
 
 
 def cpu_baseline(dim, n, p, key, dof):

@@ -357,11 +357,13 @@ int cdg2_tri_sync(cdg2_tri* t);
  * (1,0,0), (0,1,0), (0,0,1), of the monomials xi^a eta^b zeta^c ordered by total
  * degree, then by the power of zeta, then of eta, taken about the centroid);
  * volume integrals with a fully symmetric rule on the tetrahedron of degree 2k
- * (4, 14, 24 points), face integrals with a fully symmetric triangle rule of
- * degree 2k (3, 6, 12 points; the orbit parameters of both solve the moment
- * equations) so that both elements of a face use the same points; LLF and CDG2 fluxes (lifting on K^-: the smaller
- * tetrahedron of a face, ties to the lower element index; chi_e = 2) and the
- * inflow fluxes of eqs. (7)-(9) on the faces coded Gamma1 / Gamma2.  State
+ * (4, 14, 24 points; the 14-point rule has degree 5, which makes it unique),
+ * face integrals with a fully symmetric triangle rule of degree 2k (3, 6, 12
+ * points; the orbit parameters of both solve the moment equations) so that both
+ * elements of a face use the same points; LLF and CDG2 fluxes (lifting on K^-:
+ * the smaller tetrahedron of a face, ties to the lower element index;
+ * chi_e = 2) and the inflow fluxes of eqs. (7)-(9) on the faces coded Gamma1 /
+ * Gamma2.  State
  * layout: U[6][E][(k+1)(k+2)(k+3)/6] doubles, species n1, n2, n3, c1, c2, c3.
  *
  * Mesh (HOST arrays, copied at create):
