@@ -19,7 +19,7 @@ float64), inputs resident in HBM.  Prints ONE JSON line.
 
 Extras in the same line (skipped with --no-extras): the 256^2 Q2/Q4 workloads
 (graph-replayed applies, 100-step runs), the batched 256-instance run (autotuned
-schedule and the best single persistent launch) against the plain entry point
+schedule and the best single launch per stage) against the plain entry point
 (eager and graph-replayed), the adjoint (forward + gradient against forward), the
 implicit SDIRK step against the explicit steps over the same interval, the
 comparison diffusion fluxes on the exact heat solution, and the unstructured
@@ -171,8 +171,9 @@ def time_ms(fn, reps=1):
 def bench_batched(steps=50):
     """256 independent 2D instances (grid side 32..128, order 1..3, coefficients
     within +-50%): the autotuned schedule (graph-replayed), the best single
-    persistent launch per stage, against 256 sequential plain per-instance
-    rk_step runs of the same instances, eager and replayed from one graph."""
+    launch per stage for all orders (one workgroup per item or persistent),
+    against 256 sequential plain per-instance rk_step runs of the same
+    instances, eager and replayed from one graph."""
     import torch
 
     from paper_1403_1157_amd import inputs
@@ -196,11 +197,11 @@ def bench_batched(steps=50):
     bt.sync()
     ms_b = time_ms(lambda: bt.rk(work, dts, steps))
     bt.sync()
-    # the single persistent launch per stage over the cost-sorted work list (one
-    # launch for all orders, a fixed number of workgroups), best of a few sizes
+    # one launch per stage for all orders over the cost-sorted work list: one
+    # workgroup per item, or a fixed number of persistent workgroups; best of a few
     ncu = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
     pers = None
-    for eb, mult in ((32, 1), (32, 2), (32, 4), (64, 2)):
+    for eb, mult in ((32, 0), (64, 0), (32, 1), (32, 2), (32, 4), (64, 2)):
         bt.set_schedule(eb, mult * ncu, 0)
         bt.rk(work, dts, steps)
         bt.sync()
@@ -245,9 +246,10 @@ def bench_batched(steps=50):
                                   + " work list, " + ("one workgroup per work item" if sched[1] == 0 else
                                                       f"{sched[1]} persistent workgroups"))),
             "ms_batched": round(ms_b, 3),
-            "persistent_single_launch": {"schedule": list(pers[0]), "ms": round(pers[1], 3),
-                                         "meaning": "one launch per stage for all orders over the cost-sorted list, "
-                                                    f"{pers[0][1]} persistent workgroups"},
+            "single_launch": {"schedule": list(pers[0]), "ms": round(pers[1], 3),
+                              "meaning": "one launch per stage for all orders over the cost-sorted list, "
+                                         + ("one workgroup per work item" if pers[0][1] == 0 else
+                                            f"{pers[0][1]} persistent workgroups")},
             "ms_plain_sequential": round(ms_p, 3), "ms_plain_graph": round(ms_pg, 3),
             "speedup_vs_plain": round(ms_p / ms_b, 3), "speedup_vs_plain_graph": round(ms_pg / ms_b, 3),
             "gdof_steps_per_s_batched": round(dof * steps / (ms_b * 1e-3) / 1e9, 3),

@@ -40,7 +40,7 @@ struct BatchSmem {
 // stage 1: S0 = U + dt f(U); stage 2: S1 = 3/4 U + 1/4 (S0 + dt f(S0));
 // stage 3: U = 1/3 U + 2/3 (S1 + dt f(S1))  (per instance, packed buffers)
 template <typename T, int EB>
-__global__ void __launch_bounds__(6 * EB)
+__global__ void __launch_bounds__(6 * EB, 3)
 batch_stage_kernel(const BatchInst* __restrict__ insts, const WorkItem* __restrict__ items, int nitems,
                    T* U, T* S0, T* S1, int stage, int* __restrict__ flags) {
   __shared__ __align__(16) unsigned char smem[BatchSmem<T, EB>::N];
