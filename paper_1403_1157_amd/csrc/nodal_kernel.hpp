@@ -621,7 +621,16 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
   // ---- back to modes: M^{-1}, stage combination, coalesced store ------------------------
   // (+ ca U0 in the store, whose U0 loads come in chunks: all of them in flight
   // through the transform back would not fit the register budget)
-  constexpr bool combine = KIND == 2 || KIND == 5;
+  // Kinds 2, 4 and 5 take the workgroup's U0 modes through the staging area: the
+  // loads are issued before the last transform and occupy no registers while in
+  // flight (the faces are done with the shared LDS area after the first sync).
+  // Loaded at the store instead, their latency was exposed (stage 3: 635 ->
+  // 591 us per 64^3 Q2 launch).
+  constexpr bool u0_staged = KIND == 2 || KIND == 4 || KIND == 5;
+  if constexpr (u0_staged) {
+    nd_sync();
+    stage_modes<D, P, T, EB>(U0, SE, E, sm, tid);
+  }
   if constexpr (nodal_out) {
     // point values: M = |K| W_q is diagonal in the Lagrange basis of the points
     const T dti = dt * T(1.0 / g.vol);
@@ -636,9 +645,7 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
           y[m] = cb * ((m0 + v[m]) + dti * R[m] * T(1.0 / (ct.w[i] * ct.w[j] * ct.w[k])));
         }
     if constexpr (KIND == 4) {
-      // + ca U0 at the points: the workgroup's U0 modes through the staging area
-      nd_sync();
-      stage_modes<D, P, T, EB>(U0, SE, E, sm, tid);
+      // + ca U0 at the points
       wait_staged();
       nd_sync();
       T u[NM];
@@ -672,12 +679,21 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
     }
     nd_tapply3<Q, true, T>(z, y);
     if constexpr (KIND != 0) y[0] += m0;
+    if constexpr (KIND == 2 || KIND == 5) {
+      // + ca U0 (modes, the thread's own cell and species)
+      wait_staged();
+      nd_sync();
+      T u[NM];
+      staged_all<D, P, T, EB>(sm, tid, u);
+#pragma unroll
+      for (int m = 0; m < NM; ++m) y[m] = cb * y[m] + ca * u[m];
+    }
     nd_sync();
 #pragma unroll
-    for (int m = 0; m < NM; ++m) sm.buf[tid * NM + m] = KIND == 0 ? y[m] : cb * y[m];
+    for (int m = 0; m < NM; ++m) sm.buf[tid * NM + m] = KIND == 1 ? cb * y[m] : y[m];
   }
   nd_sync();
-  store_results<T, EB, NM>(sm.cell, sm.buf, U0, out, SE, ca, combine, tid, flag);
+  store_results<T, EB, NM>(sm.cell, sm.buf, U0, out, SE, ca, false, tid, flag);
   if (flag) atomicOr(flags, flag);
 }
 
