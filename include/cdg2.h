@@ -140,7 +140,9 @@ int cdg2_apply_operator(cdg2_handle* h, const void* U, void* dUdt);
  *   U1 = U + dt f(U);  U2 = 3/4 U + 1/4 (U1 + dt f(U1));
  *   U <- 1/3 U + 2/3 (U2 + dt f(U2)).
  * Each stage is one fused launch (operator + stage combination); the two
- * intermediate states live in the handle's stage buffers. */
+ * intermediate states live in the handle's stage buffers (on 3D grids with
+ * p <= 2 as values at the Gauss points of each cell, which span the same space:
+ * the same discrete step up to rounding; U itself stays modes). */
 int cdg2_rk_step(cdg2_handle* h, void* U, double dt, int nsteps);
 
 /* Size of the library's static scratch memory per GPU (64 MiB), which holds the
@@ -265,8 +267,9 @@ int cdg2_rk_adjoint_segment(cdg2_handle* h, const void* U_start, int nsteps, dou
  * of (instance, block of cells) items, either persistent (nwg > 0 workgroups
  * walk the list) or one workgroup per item (nwg = 0), or one launch per
  * polynomial order (order 2, side by side on forked streams).  cdg2_batch_rk
- * replays the stages of nsteps steps as one HIP graph.  The packed state holds instance i at element offset
- * cdg2_batch_offset(b, i), each in the DOF layout above. */
+ * replays the stages of nsteps steps as one HIP graph.  The packed state holds
+ * instance i at element offset cdg2_batch_offset(b, i), each in the DOF layout
+ * above. */
 typedef struct cdg2_batch cdg2_batch;
 
 /* Copy count configs (2D, FP64, order <= 3; else CDG2_EINVAL), allocate the
