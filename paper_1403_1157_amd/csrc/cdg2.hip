@@ -160,10 +160,13 @@ constexpr int STAGE_POINTS1 = 11;
 // The SSP-RK3 step of rk_steps keeps its intermediate states as point values.
 bool point_stages(const cdg2_handle* h) { return h->dim == 3 && h->p <= 2; }
 
-// cells per workgroup of the (cell, species) kernel: 6 * EB threads
+// cells per workgroup of the (cell, species) kernel: 6 * EB threads.  3D: 10
+// (one wavefront).  2D: 32 (three wavefronts); 21 (two wavefronts of 63 lanes)
+// for p >= 3, whose registers allow 2 waves per SIMD: the CU's 8 wave slots
+// then hold four workgroups instead of two three-wave ones.
 template <int D, int P>
 struct EsCfg {
-  static constexpr int EB = D == 3 ? 10 : 32;
+  static constexpr int EB = D == 3 ? 10 : P >= 3 ? 21 : 32;
 };
 
 template <int D, int P, typename T>
@@ -1465,16 +1468,16 @@ void tri_free(cdg2_tri* t) {
 
 hipError_t tri_launch(cdg2_tri* t, const double* U, const double* U0, double* out, double dt, double ca, double cb,
                       int stage) {
-  const int nblk = (t->E + TRI_EB - 1) / TRI_EB;
+  auto nblk = [&](int eb) { return (t->E + eb - 1) / eb; };
   if (t->k == 1)
-    hipLaunchKernelGGL((tri_kernel<1>), dim3(nblk), dim3(6 * TRI_EB), 0, t->stream, t->dprm, U, U0, out, dt, ca, cb,
-                       stage, t->flags);
+    hipLaunchKernelGGL((tri_kernel<1>), dim3(nblk(tri_eb<1>())), dim3(6 * tri_eb<1>()), 0, t->stream, t->dprm, U, U0,
+                       out, dt, ca, cb, stage, t->flags);
   else if (t->k == 2)
-    hipLaunchKernelGGL((tri_kernel<2>), dim3(nblk), dim3(6 * TRI_EB), 0, t->stream, t->dprm, U, U0, out, dt, ca, cb,
-                       stage, t->flags);
+    hipLaunchKernelGGL((tri_kernel<2>), dim3(nblk(tri_eb<2>())), dim3(6 * tri_eb<2>()), 0, t->stream, t->dprm, U, U0,
+                       out, dt, ca, cb, stage, t->flags);
   else
-    hipLaunchKernelGGL((tri_kernel<3>), dim3(nblk), dim3(6 * TRI_EB), 0, t->stream, t->dprm, U, U0, out, dt, ca, cb,
-                       stage, t->flags);
+    hipLaunchKernelGGL((tri_kernel<3>), dim3(nblk(tri_eb<3>())), dim3(6 * tri_eb<3>()), 0, t->stream, t->dprm, U, U0,
+                       out, dt, ca, cb, stage, t->flags);
   return hipGetLastError();
 }
 

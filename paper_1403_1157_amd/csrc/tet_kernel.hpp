@@ -35,10 +35,13 @@ namespace cdg2 {
 constexpr int TET_MAXB = 20;   // P_3
 constexpr int TET_MAXQ = 24;   // points of the symmetric volume rule (degree 2k)
 constexpr int TET_MAXF = 12;   // points of the symmetric face rule (degree 2k)
-// Elements per workgroup (6 threads each): 32, and 19 for P3, whose face table
-// then fits in LDS beside the exchange slots (two workgroups per CU).
+// Elements per workgroup (6 threads each): 32 for P1 (three waves at 3 waves
+// per SIMD); 21 for P2 (two waves of 63 lanes: at 2 waves per SIMD four such
+// workgroups fill a CU's 8 wave slots, where three-wave ones left two idle);
+// 19 for P3, whose face table then fits in LDS beside the exchange slots (two
+// workgroups per CU).
 template <int K>
-constexpr int tet_eb() { return K == 3 ? 19 : 32; }
+constexpr int tet_eb() { return K == 3 ? 19 : K == 2 ? 21 : 32; }
 
 // Reference tables (host-built).
 struct TetTables {

@@ -14,7 +14,7 @@
 // on Gamma1 / Gamma2 the inflow fluxes of eqs. (7)-(9).  Then f = R / |K|,
 // optionally combined with an SSP-RK3 stage in the epilogue.
 //
-// Mapping: a workgroup owns TRI_EB elements; thread (s, el) keeps the modes and
+// Mapping: a workgroup owns tri_eb<K>() elements; thread (s, el) keeps the modes and
 // the residual of species s of element el in registers.  The nonlinear terms
 // go through LDS: the volume points of the workgroup's elements at once, then the
 // edges one local edge index at a time.  Point items evaluate the chemotactic
@@ -30,7 +30,11 @@ namespace cdg2 {
 constexpr int TRI_MAXB = 10;   // P_3
 constexpr int TRI_MAXQ = 16;   // (k + 1)^2 volume points
 constexpr int TRI_MAXE = 4;    // k + 1 edge points
-constexpr int TRI_EB = 32;     // elements per workgroup (192 threads)
+// Elements per workgroup (6 threads each): 32 (three waves), and 21 for P3 (two
+// waves of 63 lanes): P3 runs at 2 waves per SIMD, whose 8 wave slots per CU
+// hold two three-wave workgroups (6 slots) but four two-wave ones.
+template <int K>
+constexpr int tri_eb() { return K == 3 ? 21 : 32; }
 
 // Reference tables (host-built).
 struct TriTables {
@@ -83,7 +87,7 @@ struct TriStride {
 template <int K>
 struct TriSmem {
   using S = TriSz<K>;
-  static constexpr int VOL = TRI_EB * TriStride<K>::VS, FAC = TRI_EB * TriStride<K>::FS;
+  static constexpr int VOL = tri_eb<K>() * TriStride<K>::VS, FAC = tri_eb<K>() * TriStride<K>::FS;
   static constexpr int N = VOL > FAC ? VOL : FAC;
   double buf[N];
   double etab[3 * S::NE * S::NB * 3];   // edge tables: [edge][point][mode][value, d/dxi, d/deta]
@@ -94,10 +98,11 @@ struct TriSmem {
 // 52 KB of LDS holds a CU to three workgroups anyway, and under the 3-wave
 // bound it spilled.
 template <int K>
-__global__ void __launch_bounds__(6 * TRI_EB, K == 3 ? 2 : 3)
+__global__ void __launch_bounds__(6 * tri_eb<K>(), K == 3 ? 2 : 3)
 tri_kernel(const TriParams* __restrict__ prm, const double* __restrict__ U, const double* U0, double* out,
            double dt, double ca, double cb, int stage, int* __restrict__ flags) {
   using S = TriSz<K>;
+  constexpr int TRI_EB = tri_eb<K>();
   constexpr int NB = S::NB, NQ = S::NQ, NE = S::NE, NT = 6 * TRI_EB;
   constexpr int VS = TriStride<K>::VS, FS = TriStride<K>::FS;
   __shared__ TriSmem<K> sm;
