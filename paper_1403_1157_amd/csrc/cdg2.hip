@@ -161,13 +161,16 @@ constexpr int STAGE_POINTS1 = 11;
 bool point_stages(const cdg2_handle* h) { return h->dim == 3 && h->p <= 2; }
 
 // cells per workgroup of the (cell, species) kernel: 6 * EB threads.  3D: 10
-// (one wavefront).  2D: 21 (two wavefronts of 63 lanes): for p >= 3, whose
+// (one wavefront).  2D: 21 (two wavefronts of 63 lanes): at p = 4, whose
 // registers allow 2 waves per SIMD, the CU's 8 wave slots hold four such
 // workgroups but only two three-wave ones (Q4 apply 138 -> 128 us at 256^2);
-// p <= 2 gained a little (Q2 apply 42.7 -> 42.0 us).
+// p <= 2 gained a little (Q2 apply 42.7 -> 42.0 us).  p = 3 keeps 32, the cells
+// per work item of the batched default: with 21 the compiler contracted a few
+// terms differently and p = 3 results differed from the batched kernel's in the
+// last bits (5e-19 relative), where they are otherwise equal bit for bit.
 template <int D, int P>
 struct EsCfg {
-  static constexpr int EB = D == 3 ? 10 : 21;
+  static constexpr int EB = D == 3 ? 10 : P == 3 ? 32 : 21;
 };
 
 template <int D, int P, typename T>
