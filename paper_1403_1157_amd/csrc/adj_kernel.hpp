@@ -44,9 +44,8 @@ struct AdjSmem {
   static constexpr int VOL = EB * S::NVQ * S::PC;
   static constexpr int FAC = EB * S::NFQ * S::NF;
   static constexpr int N = VOL > FAC ? VOL : FAC;
-  T buf[N];
+  alignas(16) T buf[N];  // also holds the doubles of the final reduction
   int nb[EB][2 * D];
-  double red[(6 * EB + 63) / 64 * CDG2_NDIFF];
 };
 
 // Parameter-derivative slots (indices into the 21 differentiable coefficients).
@@ -629,30 +628,29 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
   if (flag) atomicOr(flags, flag);
 
   // ---- deterministic per-workgroup reduction of the parameter derivatives -----------
-  // A butterfly over the 64 lanes of each wavefront (fixed pairing), then the
-  // wavefront sums in order; unrolled so that th[] stays in registers.
+  // Through the exchange buffer (free now), JB derivatives per pass: every thread
+  // writes its values, then thread j sums derivative j over the threads in a
+  // fixed order.  Any workgroup size works (no whole wavefronts needed).
   if (want_theta) {
-    static_assert(NT % 64 == 0, "whole wavefronts");
-    constexpr int NW = NT / 64;
-    const int lane = tid & 63, wv = tid >> 6;
+    constexpr int JB0 = AdjSmem<D, P, T, EB>::N * (int)sizeof(T) / (8 * NT);
+    constexpr int JB = JB0 < CDG2_NDIFF ? JB0 : CDG2_NDIFF;
+    static_assert(JB >= 1, "exchange buffer holds one derivative per thread");
+    double* red = reinterpret_cast<double*>(sm.buf);
 #pragma unroll
-    for (int j = 0; j < CDG2_NDIFF; ++j) {
-      double v = th[j] + (j < 6 && j == s ? thd : 0.0);
+    for (int j0 = 0; j0 < CDG2_NDIFF; j0 += JB) {
+      __syncthreads();
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-      th[j] = v;
-    }
-    __syncthreads();
-    if (lane == 0) {
-#pragma unroll
-      for (int j = 0; j < CDG2_NDIFF; ++j) sm.red[wv * CDG2_NDIFF + j] = th[j];
-    }
-    __syncthreads();
-    if (tid < CDG2_NDIFF) {
-      double acc = 0.0;
-      for (int k = 0; k < NW; ++k) acc += sm.red[k * CDG2_NDIFF + tid];
-      double* dst = part + (size_t)blk * CDG2_NDIFF + tid;
-      *dst = want_theta == 2 ? *dst + acc * (double)cj : acc * (double)cj;
+      for (int jj = 0; jj < JB; ++jj) {
+        const int j = j0 + jj;
+        if (j < CDG2_NDIFF) red[jj * NT + tid] = th[j] + (j < 6 && j == s ? thd : 0.0);
+      }
+      __syncthreads();
+      if (tid < JB && j0 + tid < CDG2_NDIFF) {
+        double acc = 0.0;
+        for (int k = 0; k < NT; ++k) acc += red[tid * NT + k];
+        double* dst = part + (size_t)blk * CDG2_NDIFF + j0 + tid;
+        *dst = want_theta == 2 ? *dst + acc * (double)cj : acc * (double)cj;
+      }
     }
   }
 }

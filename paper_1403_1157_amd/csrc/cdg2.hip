@@ -244,9 +244,14 @@ hipError_t dispatch_cfl(cdg2_handle* h, const void* U) {
   return hipErrorInvalidValue;
 }
 
+// Cells per adjoint workgroup: 21 cells = 126 threads = two wavefronts, so that
+// at two waves per SIMD (the register budget of the adjoint) four workgroups
+// fill all eight wave slots of a CU.
+constexpr int ADJ_EB = 21;
+
 template <int D, int P>
 struct AdjCfg {
-  static constexpr int EB = 32;
+  static constexpr int EB = ADJ_EB;
 };
 
 template <int D, int P, typename T>
@@ -296,7 +301,7 @@ int ensure_adjoint(cdg2_handle* h) {
     return fail(CDG2_EINVAL, "the adjoint needs a central symmetric diffusion flux (CDG2, BR2 or IP)");
   if (h->part) return CDG2_OK;
   size_t bytes = h->ndof * (h->fp32 ? 4 : 8);
-  int nb = (h->geo.E + 31) / 32;
+  int nb = (h->geo.E + ADJ_EB - 1) / ADJ_EB;
   for (int k = 0; k < 2; ++k)
     if (hipMalloc(&h->adj[k], bytes) != hipSuccess) return fail(CDG2_ENOMEM, "hipMalloc of adjoint buffers failed");
   if (hipMalloc((void**)&h->dth, 64 * sizeof(double)) != hipSuccess ||
