@@ -41,8 +41,11 @@ struct AdjSz {
 template <int D, int P, typename T, int EB>
 struct AdjSmem {
   using S = AdjSz<D, P>;
-  static constexpr int VOL = EB * S::NVQ * S::PC;
-  static constexpr int FAC = EB * S::NFQ * S::NF;
+  // per-cell strides, odd in elements of T so that the cells of the workgroup
+  // start on different LDS banks (the plain ones are multiples of 32 dwords in 3D)
+  static constexpr int VST = (S::NVQ * S::PC) | 1, FST = (S::NFQ * S::NF) | 1;
+  static constexpr int VOL = EB * VST;
+  static constexpr int FAC = EB * FST;
   static constexpr int N = VOL > FAC ? VOL : FAC;
   alignas(16) T buf[N];  // also holds the doubles of the final reduction
   int nb[EB][2 * D];
@@ -57,6 +60,7 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
                                           AdjSmem<D, P, T, EB>& sm) {
   using S = AdjSz<D, P>;
   constexpr int Q = S::Q, NM = S::NM, NF = S::NF, NFACE = 2 * D, PC = S::PC, NVQ = S::NVQ;
+  constexpr int VST = AdjSmem<D, P, T, EB>::VST, FST = AdjSmem<D, P, T, EB>::FST;
   constexpr int NT = 6 * EB;
   const Tables& tb = prm.tb;
   const Geo& g = prm.g;
@@ -168,7 +172,7 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
   const bool grads = s == S_N1 || s == S_C1 || s == S_C3;
   const int gslot = s == S_N1 ? 4 : s == S_C1 ? 4 + D : 4 + 2 * D;
   constexpr int AG1 = 4 + 3 * D, AG2 = AG1 + D, AL3 = AG2 + D;   // adjoint slots
-  T* V = sm.buf;
+  T* V = sm.buf;   // [EB][VST]: NVQ slots of PC points, then the pad
   constexpr int LA = D - 1;
   constexpr int LST = ipow(Q, D - 1);
   const double(*Bt0)[CDG2_MAXQ] = tb.B;
@@ -189,17 +193,17 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
       }
       tapply_lo<D, Q, false, T>(tv, o, Bt0, Bt0);
 #pragma unroll
-      for (int q = 0; q < PC; ++q) V[(el * NVQ + prod) * PC + q] = o[q];
+      for (int q = 0; q < PC; ++q) V[el * VST + (prod) * PC + q] = o[q];
       if (grads) {
 #pragma unroll
         for (int a = 0; a < D - 1; ++a) {
           tapply_lo<D, Q, false, T>(tv, o, a == 0 ? tb.Bd : tb.B, a == 1 ? tb.Bd : tb.B);
 #pragma unroll
-          for (int q = 0; q < PC; ++q) V[(el * NVQ + gslot + a) * PC + q] = o[q] * T(g.ih[a]);
+          for (int q = 0; q < PC; ++q) V[el * VST + (gslot + a) * PC + q] = o[q] * T(g.ih[a]);
         }
         tapply_lo<D, Q, false, T>(td, o, Bt0, Bt0);
 #pragma unroll
-        for (int q = 0; q < PC; ++q) V[(el * NVQ + gslot + LA) * PC + q] = o[q] * T(g.ih[LA]);
+        for (int q = 0; q < PC; ++q) V[el * VST + (gslot + LA) * PC + q] = o[q] * T(g.ih[LA]);
       }
     }
     // adjoint fields: grad psi_n1, grad psi_n2, psi_c1
@@ -219,18 +223,18 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
       if (s == S_C1) {
         tapply_lo<D, Q, false, T>(tv, o, Bt0, Bt0);
 #pragma unroll
-        for (int q = 0; q < PC; ++q) V[(el * NVQ + AL3) * PC + q] = o[q];
+        for (int q = 0; q < PC; ++q) V[el * VST + (AL3) * PC + q] = o[q];
       } else {
         const int base = s == S_N1 ? AG1 : AG2;
 #pragma unroll
         for (int a = 0; a < D - 1; ++a) {
           tapply_lo<D, Q, false, T>(tv, o, a == 0 ? tb.Bd : tb.B, a == 1 ? tb.Bd : tb.B);
 #pragma unroll
-          for (int q = 0; q < PC; ++q) V[(el * NVQ + base + a) * PC + q] = o[q] * T(g.ih[a]);
+          for (int q = 0; q < PC; ++q) V[el * VST + (base + a) * PC + q] = o[q] * T(g.ih[a]);
         }
         tapply_lo<D, Q, false, T>(td, o, Bt0, Bt0);
 #pragma unroll
-        for (int q = 0; q < PC; ++q) V[(el * NVQ + base + LA) * PC + q] = o[q] * T(g.ih[LA]);
+        for (int q = 0; q < PC; ++q) V[el * VST + (base + LA) * PC + q] = o[q] * T(g.ih[LA]);
       }
     }
     __syncthreads();
@@ -239,7 +243,7 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
     // 4+D+a d/d grad c1, 4+2D+a d/d grad c3 (gradient tests, scaled by 1/h_a)
     for (int it = tid; it < EB * PC; it += NT) {
       const int l = it / PC, q = it % PC;
-      T* x = V + l * NVQ * PC + q;
+      T* x = V + l * VST + q;
       const T n1 = x[0], n2 = x[PC], c1 = x[2 * PC], c3 = x[3 * PC];
       const T d11 = c1 + T(c[K_XT11]), d13 = c3 + T(c[K_XT13]), d21 = c1 + T(c[K_XT21]),
               d22 = n1 + T(c[K_XT22]);
@@ -308,7 +312,7 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
     if (prod >= 0) {
       T r[NF], acc[NF], sum[NF];
 #pragma unroll
-      for (int q = 0; q < PC; ++q) r[q] = V[(el * NVQ + prod) * PC + q];
+      for (int q = 0; q < PC; ++q) r[q] = V[el * VST + (prod) * PC + q];
       tapply_lo<D, Q, true, T>(r, sum, Bt0, Bt0);    // value test, layer factor B[lc][k]
       T dz[NF];
 #pragma unroll
@@ -317,13 +321,13 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
 #pragma unroll
         for (int a = 0; a < D - 1; ++a) {
 #pragma unroll
-          for (int q = 0; q < PC; ++q) r[q] = V[(el * NVQ + gslot + a) * PC + q];
+          for (int q = 0; q < PC; ++q) r[q] = V[el * VST + (gslot + a) * PC + q];
           tapply_lo<D, Q, true, T>(r, acc, a == 0 ? tb.Bd : tb.B, a == 1 ? tb.Bd : tb.B);
 #pragma unroll
           for (int m = 0; m < NF; ++m) sum[m] += acc[m];
         }
 #pragma unroll
-        for (int q = 0; q < PC; ++q) r[q] = V[(el * NVQ + gslot + LA) * PC + q];
+        for (int q = 0; q < PC; ++q) r[q] = V[el * VST + (gslot + LA) * PC + q];
         tapply_lo<D, Q, true, T>(r, dz, Bt0, Bt0);
       }
 #pragma unroll
@@ -335,7 +339,7 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
 
   // ---- faces ------------------------------------------------------------------------
   const bool diss = !(g.llf_cells && s > S_N2);
-  T* Fx = sm.buf;   // [EB][26][NF]
+  T* Fx = sm.buf;   // [EB][FST]: 26 slots of NF points, then the pad
   const int vslot = prod;
   const int dslot = s == S_N1 ? 8 : s == S_C1 ? 9 : s == S_C3 ? 10 : -1;
 #pragma unroll
@@ -414,11 +418,11 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
         own_tr(u, sg, false, tr);
         tapply_lo<D, Q, false, T>(tr, o, Tb0, Tb0);
 #pragma unroll
-        for (int t = 0; t < NF; ++t) Fx[(el * 26 + vslot) * NF + t] = o[t];
+        for (int t = 0; t < NF; ++t) Fx[el * FST + (vslot) * NF + t] = o[t];
         nb_tr(su, T(1), false, tr);
         tapply_lo<D, Q, false, T>(tr, o, Tb0, Tb0);
 #pragma unroll
-        for (int t = 0; t < NF; ++t) Fx[(el * 26 + 4 + vslot) * NF + t] = o[t];
+        for (int t = 0; t < NF; ++t) Fx[el * FST + (4 + vslot) * NF + t] = o[t];
       }
       if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
       {
@@ -428,10 +432,10 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
         if (dslot >= 0) {
           tapply_lo<D, Q, false, T>(d0, o, Tb0, Tb0);
 #pragma unroll
-          for (int t = 0; t < NF; ++t) Fx[(el * 26 + dslot) * NF + t] = o[t];
+          for (int t = 0; t < NF; ++t) Fx[el * FST + (dslot) * NF + t] = o[t];
           tapply_lo<D, Q, false, T>(d1, o, Tb0, Tb0);
 #pragma unroll
-          for (int t = 0; t < NF; ++t) Fx[(el * 26 + dslot + 3) * NF + t] = o[t];
+          for (int t = 0; t < NF; ++t) Fx[el * FST + (dslot + 3) * NF + t] = o[t];
         }
 #pragma unroll
         for (int J = 0; J < NF; ++J) sdu[J] = d0[J] + d1[J];
@@ -441,7 +445,7 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
       jump(u, su, T(1), jm);
       tapply_lo<D, Q, false, T>(jm, o, Tb0, Tb0);
 #pragma unroll
-      for (int t = 0; t < NF; ++t) Fx[(el * 26 + 20 + s) * NF + t] = o[t];
+      for (int t = 0; t < NF; ++t) Fx[el * FST + (20 + s) * NF + t] = o[t];
       if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
       {
         T d0[NF], d1[NF];
@@ -459,7 +463,7 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
       }
       tapply_lo<D, Q, false, T>(jv, o, Tb0, Tb0);
 #pragma unroll
-      for (int t = 0; t < NF; ++t) Fx[(el * 26 + 14 + s) * NF + t] = o[t];
+      for (int t = 0; t < NF; ++t) Fx[el * FST + (14 + s) * NF + t] = o[t];
     }
     __syncthreads();
     // face point pass: derivatives of sum_s g_s dpsi_s with respect to the own
@@ -467,7 +471,7 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
     // 7 d/d(d_a c1_o), 8 d/d(d_a c3_o); weighted by the tangential weights
     for (int it = tid; it < EB * NF; it += NT) {
       const int l = it / NF, t = it % NF;
-      T* x = Fx + l * 26 * NF + t;
+      T* x = Fx + l * FST + t;
       const int nbl = sm.nb[l][f];
       const bool ok = e0 + l < E;
       T wt;
@@ -567,7 +571,7 @@ __device__ __forceinline__ void adj_block(const Params& prm, const T* __restrict
     __syncthreads();
     // species pass: linear face terms applied to v, nonlinear derivatives spread
     {
-      const T* x = Fx + el * 26 * NF;
+      const T* x = Fx + el * FST;
       T gp[NF], gh[NF], dp[NF], dh[NF];
 #pragma unroll
       for (int t = 0; t < NF; ++t) gp[t] = x[s * NF + t];

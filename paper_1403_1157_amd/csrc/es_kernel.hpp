@@ -67,8 +67,14 @@ struct EsSmem {
   static constexpr int CB = BYTES % 16 == 0 ? 16 : BYTES % 12 == 0 ? 12 : 4;
   static constexpr int LS = CB == 4 ? 4 : 16;
   static constexpr int NCH = BYTES / CB;
-  static constexpr int VOL = EB * NV * S::PC;   // NV exchange slots per volume point
-  static constexpr int FAC = EB * S::NFQ * S::NF;
+  // Per-cell strides of the exchange slots, odd in elements of T: with the plain
+  // strides (3D Q3: 13 x 16 and 14 x 16 doubles) every cell of the workgroup
+  // starts on the same LDS bank, and lanes reading the same slot of different
+  // cells collide; odd strides spread the cells over the banks.
+  static constexpr int VST = (NV * S::PC) | 1;   // NV exchange slots per volume point
+  static constexpr int FST = (S::NFQ * S::NF) | 1;
+  static constexpr int VOL = EB * VST;
+  static constexpr int FAC = EB * FST;
   static constexpr int STG = STAGED ? 6 * EB * NCH * LS / (int)sizeof(T) : 0;
   static constexpr int N0 = VOL > FAC + XTRA ? VOL : FAC + XTRA;   // XTRA values after the face slots
   static constexpr int N = N0 > STG ? N0 : STG;
@@ -349,6 +355,7 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
 
   // ---- own modes, neighbour table ------------------------------------------------
   constexpr bool STAGED = EsSmem<D, P, T, EB>::STAGED;
+  constexpr int VST = EsSmem<D, P, T, EB>::VST, FST = EsSmem<D, P, T, EB>::FST;
   T u[NM], R[NM];
   for (int it = tid; it < EB * NFACE; it += NT) {
     int l = it / NFACE, f = it % NFACE;
@@ -417,18 +424,18 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
   const int prod = s == S_N1 ? 0 : s == S_N2 ? 1 : s == S_C1 ? 2 : s == S_C3 ? 3 : -1;
   const bool grads = s == S_N1 || s == S_C1 || s == S_C3;
   const int gslot = s == S_N1 ? 4 : s == S_C1 ? 4 + D : 4 + 2 * D;
-  T* V = sm.buf;   // [EB][NVQ][PC]
+  T* V = sm.buf;   // [EB][VST]: NVQ slots of PC points, then the pad
   constexpr int LA = D - 1;   // layer axis
   constexpr int LST = ipow(Q, D - 1);
   const double(*Bt0)[CDG2_MAXQ] = tb.B;
   for (int lc = 0; lc < Q; ++lc) {
     __syncthreads();
-    if (prod >= 0) produce_layer<D, Q, T>(tb, g, u, lc, V + el * NVQ * PC, prod, grads ? gslot : -1);
+    if (prod >= 0) produce_layer<D, Q, T>(tb, g, u, lc, V + el * VST, prod, grads ? gslot : -1);
     __syncthreads();
     // point pass: chemotactic fluxes and the alpha reaction term, weighted
     for (int it = tid; it < EB * PC; it += NT) {
       const int l = it / PC, q = it % PC;
-      T* v = V + l * NVQ * PC + q;
+      T* v = V + l * VST + q;
       const T n1 = v[0], n2 = v[PC], c1 = v[2 * PC], c3 = v[3 * PC];
       const T d11 = c1 + T(c[K_XT11]), d13 = c3 + T(c[K_XT13]), d21 = c1 + T(c[K_XT21]),
               d22 = n1 + T(c[K_XT22]);
@@ -466,7 +473,7 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
       T r[NF], acc[NF];
       if (s == S_C1) {
 #pragma unroll
-        for (int q = 0; q < PC; ++q) r[q] = V[(el * NVQ + 2 * D) * PC + q];
+        for (int q = 0; q < PC; ++q) r[q] = V[el * VST + 2 * D * PC + q];
         tapply_lo<D, Q, true, T>(r, acc, Bt0, Bt0);
 #pragma unroll
         for (int k = 0; k < Q; ++k)
@@ -480,13 +487,13 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
 #pragma unroll
         for (int a = 0; a < D - 1; ++a) {
 #pragma unroll
-          for (int q = 0; q < PC; ++q) r[q] = V[(el * NVQ + base + a) * PC + q];
+          for (int q = 0; q < PC; ++q) r[q] = V[el * VST + (base + a) * PC + q];
           tapply_lo<D, Q, true, T>(r, acc, a == 0 ? tb.Bd : tb.B, a == 1 ? tb.Bd : tb.B);
 #pragma unroll
           for (int m = 0; m < NF; ++m) sum[m] += acc[m];
         }
 #pragma unroll
-        for (int q = 0; q < PC; ++q) r[q] = V[(el * NVQ + base + LA) * PC + q];
+        for (int q = 0; q < PC; ++q) r[q] = V[el * VST + (base + LA) * PC + q];
         tapply_lo<D, Q, true, T>(r, acc, Bt0, Bt0);
 #pragma unroll
         for (int k = 0; k < Q; ++k)
@@ -503,7 +510,7 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
   // face exchange slots (x NF): 0..3 values n1 n2 c1 c3 own, 4..7 same neighbour,
   // 8..10 d_a n1 c1 c3 own, 11..13 neighbour.  After the point pass: 0 lambda/2,
   // 1 -F1.n_o/2 sum, 2 -F2.n_o/2 sum, 3..5 inflow fluxes n1, n2, c2 (boundary).
-  T* Fx = sm.buf;
+  T* Fx = sm.buf;   // [EB][FST]: 14 slots of NF points, then the pad
   const int vslot = prod;   // value slot of this species (or -1)
   const int dslot = s == S_N1 ? 8 : s == S_C1 ? 9 : s == S_C3 ? 10 : -1;
   // the face axis is unrolled (a compile-time constant, so that the register
@@ -563,19 +570,19 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
       T o[NF];
       tapply_lo<D, Q, false, T>(uo, o, Tb0, Tb0);
 #pragma unroll
-      for (int t = 0; t < NF; ++t) Fx[(el * 14 + vslot) * NF + t] = o[t];
+      for (int t = 0; t < NF; ++t) Fx[el * FST + vslot * NF + t] = o[t];
       tapply_lo<D, Q, false, T>(un, o, Tb0, Tb0);
 #pragma unroll
-      for (int t = 0; t < NF; ++t) Fx[(el * 14 + 4 + vslot) * NF + t] = o[t];
+      for (int t = 0; t < NF; ++t) Fx[el * FST + (4 + vslot) * NF + t] = o[t];
     }
     if (dslot >= 0) {
       T o[NF];
       tapply_lo<D, Q, false, T>(duo, o, Tb0, Tb0);
 #pragma unroll
-      for (int t = 0; t < NF; ++t) Fx[(el * 14 + dslot) * NF + t] = o[t];
+      for (int t = 0; t < NF; ++t) Fx[el * FST + dslot * NF + t] = o[t];
       tapply_lo<D, Q, false, T>(dun, o, Tb0, Tb0);
 #pragma unroll
-      for (int t = 0; t < NF; ++t) Fx[(el * 14 + dslot + 3) * NF + t] = o[t];
+      for (int t = 0; t < NF; ++t) Fx[el * FST + (dslot + 3) * NF + t] = o[t];
     }
     // the species pass needs only the weighted derivative sum (own is K^- on the
     // high face, sg = 1) and the jump: formed now, so that the four trace arrays
@@ -588,7 +595,7 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
     // face point pass
     for (int it = tid; it < EB * NF; it += NT) {
       const int l = it / NF, t = it % NF;
-      T* x = Fx + l * 14 * NF + t;
+      T* x = Fx + l * FST + t;
       const int nbl = sm.nb[l][f];
       const T c1o = x[2 * NF];
       if (nbl >= 0) {
@@ -637,7 +644,7 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
     // plus the linear face terms; spread onto the normal modes
     {
       T gp[NF], gh[NF];
-      const T* x = Fx + el * 14 * NF;
+      const T* x = Fx + el * FST;
       if (nb >= 0) {
         T jp[NF];
         tapply_lo<D, Q, false, T>(jm, jp, Tb0, Tb0);

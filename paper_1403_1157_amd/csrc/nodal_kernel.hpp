@@ -213,7 +213,10 @@ constexpr int ND_NVQ = 15;
 template <int P>
 constexpr int nd_park_stride() { return 2 * (P + 1) * (P + 1); }
 template <int P, typename T, int EB>
-using NdSmem = EsSmem<3, P, T, EB, ND_NVQ, 6 * EB * nd_park_stride<P>()>;
+using NdSmem = EsSmem<3, P, T, EB, ND_NVQ, 6 * EB * nd_park_stride<P>() + 4>;
+// Start of the parked values: after the face slots, rounded up to 4 elements.
+template <int P, typename T, int EB>
+constexpr int nd_park_base() { return (NdSmem<P, T, EB>::FAC + 3) & ~3; }
 
 // Workgroup barrier that is also a scheduling fence: no instruction moves across
 // it, so the compiler cannot start a later layer's or face's arithmetic early and
@@ -247,7 +250,8 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
   constexpr int Q = S::Q, NM = S::NM, NF = S::NF, NFACE = S::NFACE, PC = S::PC;
   constexpr int NVQ = ND_NVQ, NT = 6 * EB;
   static_assert(NdSmem<P, T, EB>::STAGED, "3D staging");
-  static_assert(EB * NVQ * PC <= NdSmem<P, T, EB>::N && EB * S::NFQ * NF + NT * nd_park_stride<P>() <= NdSmem<P, T, EB>::N &&
+  constexpr int FST = NdSmem<P, T, EB>::FST;
+  static_assert(EB * NVQ * PC <= NdSmem<P, T, EB>::N && nd_park_base<P, T, EB>() + NT * nd_park_stride<P>() <= NdSmem<P, T, EB>::N &&
                     NT * NM <= NdSmem<P, T, EB>::N,
                 "LDS union");
   const Tables& tb = prm.tb;
@@ -515,20 +519,20 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
     if (fvslot >= 0) {
 #pragma unroll
       for (int t = 0; t < NF; ++t) {
-        Fx[(el * 14 + fvslot) * NF + t] = m0 + uo[t];
-        Fx[(el * 14 + 4 + fvslot) * NF + t] = w0 + un[t];
+        Fx[el * FST + (fvslot) * NF + t] = m0 + uo[t];
+        Fx[el * FST + (4 + fvslot) * NF + t] = w0 + un[t];
       }
     }
     if (dslot >= 0) {
 #pragma unroll
       for (int t = 0; t < NF; ++t) {
-        Fx[(el * 14 + dslot) * NF + t] = duo[t];
-        Fx[(el * 14 + dslot + 3) * NF + t] = dun[t];
+        Fx[el * FST + (dslot) * NF + t] = duo[t];
+        Fx[el * FST + (dslot + 3) * NF + t] = dun[t];
       }
     }
     // the jump and the derivative sum wait in LDS during the point pass (no
     // registers held through it)
-    T* park = sm.buf + EB * S::NFQ * NF + tid * nd_park_stride<P>();
+    T* park = sm.buf + nd_park_base<P, T, EB>() + tid * nd_park_stride<P>();
     // weights of the own side and the neighbour in the average (own is K^- on the
     // high face, sg = 1)
     const T wo = T(sg ? g.wm : g.wp), wn = T(sg ? g.wp : g.wm);
@@ -542,7 +546,7 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
     const int b0 = a == 0 ? 1 : 0;   // first tangential axis
     for (int it = tid; it < EB * NF; it += NT) {
       const int l = it / NF, t = it % NF;
-      T* x = Fx + l * 14 * NF + t;
+      T* x = Fx + l * FST + t;
       const int nbl = sm.nb[l][f];
       const T c1o = x[2 * NF];
       if (nbl >= 0) {
@@ -589,7 +593,7 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
     // species pass: all face terms at the face points, weighted, spread onto the
     // Lagrange functions of the normal line through each point
     {
-      const T* x = Fx + el * 14 * NF;
+      const T* x = Fx + el * FST;
       const T ar = T(g.area[a]);
       const T so = sg ? T(1) : T(-1);
       const T pen = T(g.pen_c * tb.liftc * g.ih[a]) * as;
@@ -603,7 +607,7 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
       const T li = T(in ? 1 : 0);   // linear face terms on interior faces only
       const T le0 = T(tb.Le[sg][0]), le1 = T(tb.Le[sg][1]), dle0 = T(tb.dLe[sg][0]), dle1 = T(tb.dLe[sg][1]);
       const T le2 = T(tb.Le[sg][Q - 1]), dle2 = T(tb.dLe[sg][Q - 1]);
-      const T* park = sm.buf + EB * S::NFQ * NF + tid * nd_park_stride<P>();
+      const T* park = sm.buf + nd_park_base<P, T, EB>() + tid * nd_park_stride<P>();
 #pragma unroll
       for (int t = 0; t < NF; ++t) {
         const T jm = park[t], sd = park[NF + t];
