@@ -101,12 +101,13 @@ template <int K>
 constexpr int tet_frow() { return TetSz<K>::NB * 4 + 2; }
 
 // Per-element (and per-thread) strides of the LDS slots, odd in doubles: the
-// plain strides (15 QC, 14 NF, 2 NF doubles) put the 32 elements of a species on
-// 2 to 16 banks (up to a 16-way conflict); odd strides spread them over all.
+// plain even strides (15 QC at P1 and P3, 14 NF, 2 NF doubles) put the elements
+// of a species on 2 to 16 banks (up to a 16-way conflict); odd strides spread
+// them over all.  (15 QC is odd at P2 and stays as it is.)
 template <int K>
 struct TetStride {
   using S = TetSz<K>;
-  static constexpr int VS = S::NVQ * S::QC + 1, FS = S::NFQ * S::NF + 1, PS = 2 * S::NF + 1;
+  static constexpr int VS = (S::NVQ * S::QC) | 1, FS = (S::NFQ * S::NF) | 1, PS = 2 * S::NF + 1;
 };
 
 template <int K>
@@ -162,7 +163,7 @@ tet_kernel(const TetParams* __restrict__ prm, const double* __restrict__ U, cons
   const double as = c[K_MU1 + s];
 
   // ---- volume, QC points at a time ---------------------------------------------------
-  double* V = sm.buf;   // [EB][VS]: NVQ slots of QC points, then one pad
+  double* V = sm.buf;   // [EB][VS]: NVQ slots of QC points (VS odd)
   const int vslot = s == S_N1 ? 0 : s == S_N2 ? 1 : s == S_C1 ? 2 : s == S_C3 ? 3 : s == S_N3 ? 13 : 14;
   const int gslot = s == S_N1 ? 4 : s == S_C1 ? 7 : s == S_C3 ? 10 : -1;
   // linear reactions: n1 -d1 n1; n2 -d2 n2; n3 (d1 - gamma) n1 + d2 n2; c1 f1 n3 (+ alpha
