@@ -334,6 +334,124 @@ __device__ __forceinline__ void recip4(T a, T b, T c, T d, T& ra, T& rb, T& rc, 
   rd = rcd * c;
 }
 
+// Face point pass of the Cartesian kernels, face f = 2 a + sg of every cell of the
+// workgroup.  Exchange slots of point t of cell l, x = Fx + l FST + t (stride NF):
+// 0..3 own n1 n2 c1 c3, 4..7 the neighbour's, 8..10 own normal derivatives of n1
+// c1 c3, 11..13 the neighbour's.  Written: on an interior face lambda / 2 (0) and
+// the averaged chemotactic normal fluxes -(F1 . n) / 2, -(F2 . n) / 2 (1, 2); on a
+// boundary face zeros there and the inflow fluxes of n1, n2, c2 (3..5).
+// The EB NF points go to the threads in whole rounds of one point per thread.
+// With HALVES, the remaining points, when twice their number fits the workgroup,
+// are split in two halves (own side, neighbour side) on a pair of adjacent lanes
+// joined by two-lane shuffles: 3D Q2 has 90 points for 60 threads, one round and
+// 30 points on 60 lanes instead of a second round at half occupancy.
+template <int D, int Q, int NF, int EB, int FST, bool HALVES_OK, typename T>
+__device__ __forceinline__ void face_points(T* Fx, const int (*nbt)[2 * D], int f, int sg, int b0,
+                                            const double* c, const Geo& g, const Tables& tb, int e0, int E,
+                                            int tid, int& flag) {
+  constexpr int NT = 6 * EB, NPT = EB * NF, NFULL = NPT / NT * NT, REM = NPT - NFULL;
+  constexpr bool HALVES = HALVES_OK && REM > 0 && 2 * REM <= NT;
+  // boundary point: no LLF terms, the inflow fluxes
+  auto inflow = [&](T* x, int l, int t, int nbl, T c1o) {
+    T q1 = T(0), q2 = T(0), q5 = T(0);
+    if (nbl == -1) {
+      if (c1o - T(c[K_C1S]) > T(0)) q1 = T(c[K_MU1] * c[K_BE1]);
+      const double xc = (cell_coord<D>(g, cell_of<D>(g, e0 + l), b0) + tb.x[t % Q]) * g.h[b0];
+      if (xc >= g.g1in[0] && xc <= g.g1in[1]) q5 = T(c[K_NU2] * c[K_SIG]);
+    } else if (nbl == -2) {
+      if (c1o - T(c[K_C1SS]) > T(0)) q2 = T(c[K_MU2] * c[K_BE2]);
+    }
+    x[0] = T(0);
+    x[NF] = T(0);
+    x[2 * NF] = T(0);
+    x[3 * NF] = q1;
+    x[4 * NF] = q2;
+    x[5 * NF] = q5;
+  };
+  for (int it = tid; it < (HALVES ? NFULL : NPT); it += NT) {
+    const int l = it / NF, t = it % NF;
+    T* x = Fx + l * FST + t;
+    const int nbl = nbt[l][f];
+    const T c1o = x[2 * NF];
+    if (nbl >= 0) {
+      const T so = sg ? T(1) : T(-1);
+      const T n1o = x[0], n2o = x[NF], c3o = x[3 * NF];
+      const T n1n = x[4 * NF], n2n = x[5 * NF], c1n = x[6 * NF], c3n = x[7 * NF];
+      const T dn1o = x[8 * NF], dc1o = x[9 * NF], dc3o = x[10 * NF];
+      const T dn1n = x[11 * NF], dc1n = x[12 * NF], dc3n = x[13 * NF];
+      const T t11 = T(c[K_XT11]), t13 = T(c[K_XT13]), t21 = T(c[K_XT21]), t22 = T(c[K_XT22]);
+      const T d11o = c1o + t11, d13o = c3o + t13, d21o = c1o + t21, d22o = n1o + t22;
+      const T d11n = c1n + t11, d13n = c3n + t13, d21n = c1n + t21, d22n = n1n + t22;
+      if (e0 + l < E && !(d11o > T(0) && d13o > T(0) && d21o > T(0) && d22o > T(0) &&
+                          d11n > T(0) && d13n > T(0) && d21n > T(0) && d22n > T(0)))
+        flag |= FLAG_DOMAIN;
+      T r11o, r13o, r21o, r22o, r11n, r13n, r21n, r22n;
+      recip4(d11o, d13o, d21o, d22o, r11o, r13o, r21o, r22o);
+      recip4(d11n, d13n, d21n, d22n, r11n, r13n, r21n, r22n);
+      const T w1o = so * (T(c[K_X011]) * dc1o * r11o + T(c[K_X013]) * dc3o * r13o);
+      const T w2o = so * (T(c[K_X021]) * dc1o * r21o - T(c[K_X022]) * dn1o * r22o);
+      const T w1n = so * (T(c[K_X011]) * dc1n * r11n + T(c[K_X013]) * dc3n * r13n);
+      const T w2n = so * (T(c[K_X021]) * dc1n * r21n - T(c[K_X022]) * dn1n * r22n);
+      const T lam = fmax(fmax(fabs(w1o), fabs(w2o)), fmax(fabs(w1n), fabs(w2n)));
+      x[0] = T(0.5) * lam;
+      x[NF] = -T(0.5) * (n1o * w1o + n1n * w1n);
+      x[2 * NF] = -T(0.5) * (n2o * w2o + n2n * w2n);
+    } else {
+      T q1 = T(0), q2 = T(0), q5 = T(0);
+      if (nbl == -1) {
+        if (c1o - T(c[K_C1S]) > T(0)) q1 = T(c[K_MU1] * c[K_BE1]);
+        const double xc = (cell_coord<D>(g, cell_of<D>(g, e0 + l), b0) + tb.x[t % Q]) * g.h[b0];
+        if (xc >= g.g1in[0] && xc <= g.g1in[1]) q5 = T(c[K_NU2] * c[K_SIG]);
+      } else if (nbl == -2) {
+        if (c1o - T(c[K_C1SS]) > T(0)) q2 = T(c[K_MU2] * c[K_BE2]);
+      }
+      x[0] = T(0);
+      x[NF] = T(0);
+      x[2 * NF] = T(0);
+      x[3 * NF] = q1;
+      x[4 * NF] = q2;
+      x[5 * NF] = q5;
+    }
+  }
+  if constexpr (HALVES) {
+    static_assert(NT % 2 == 0, "lane pairs");
+    const int hi = tid >> 1, side = tid & 1;   // side 0 own, 1 neighbour
+    const bool act = hi < REM;
+    const int it = NFULL + (act ? hi : 0);
+    const int l = it / NF, t = it % NF;
+    T* x = Fx + l * FST + t;
+    const int nbl = nbt[l][f];
+    T m = T(0), p1 = T(0), p2 = T(0);
+    if (act && nbl >= 0) {
+      const T so = sg ? T(1) : T(-1);
+      const T t11 = T(c[K_XT11]), t13 = T(c[K_XT13]), t21 = T(c[K_XT21]), t22 = T(c[K_XT22]);
+      const int vb = side ? 4 : 0, db = side ? 11 : 8;
+      const T n1 = x[vb * NF], n2 = x[(vb + 1) * NF], c1 = x[(vb + 2) * NF], c3 = x[(vb + 3) * NF];
+      const T dn1 = x[db * NF], dc1 = x[(db + 1) * NF], dc3 = x[(db + 2) * NF];
+      const T d11 = c1 + t11, d13 = c3 + t13, d21 = c1 + t21, d22 = n1 + t22;
+      if (e0 + l < E && !(d11 > T(0) && d13 > T(0) && d21 > T(0) && d22 > T(0))) flag |= FLAG_DOMAIN;
+      T r11, r13, r21, r22;
+      recip4(d11, d13, d21, d22, r11, r13, r21, r22);
+      const T w1 = so * (T(c[K_X011]) * dc1 * r11 + T(c[K_X013]) * dc3 * r13);
+      const T w2 = so * (T(c[K_X021]) * dc1 * r21 - T(c[K_X022]) * dn1 * r22);
+      m = fmax(fabs(w1), fabs(w2));
+      p1 = n1 * w1;
+      p2 = n2 * w2;
+    }
+    // every lane takes part in the shuffles; the lanes of a point are 2k, 2k + 1
+    const T m2 = __shfl_xor(m, 1, 64), q1 = __shfl_xor(p1, 1, 64), q2 = __shfl_xor(p2, 1, 64);
+    if (act && side == 0) {
+      if (nbl >= 0) {
+        x[0] = T(0.5) * fmax(m, m2);
+        x[NF] = -T(0.5) * (p1 + q1);
+        x[2 * NF] = -T(0.5) * (p2 + q2);
+      } else {
+        inflow(x, l, t, nbl, x[2 * NF]);
+      }
+    }
+  }
+}
+
 template <int D, int P, typename T, int EB>
 __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict__ U, const T* U0, T* out,
                                          T dt, T ca, T cb, int stage, int* __restrict__ flags, int e0,
@@ -593,52 +711,7 @@ __device__ __forceinline__ void es_block(const Params& prm, const T* __restrict_
     for (int J = 0; J < NF; ++J) sd[J] = wo * duo[J] + wn * dun[J];
     __syncthreads();
     // face point pass
-    for (int it = tid; it < EB * NF; it += NT) {
-      const int l = it / NF, t = it % NF;
-      T* x = Fx + l * FST + t;
-      const int nbl = sm.nb[l][f];
-      const T c1o = x[2 * NF];
-      if (nbl >= 0) {
-        const T so = sg ? T(1) : T(-1);
-        const T n1o = x[0], n2o = x[NF], c3o = x[3 * NF];
-        const T n1n = x[4 * NF], n2n = x[5 * NF], c1n = x[6 * NF], c3n = x[7 * NF];
-        const T dn1o = x[8 * NF], dc1o = x[9 * NF], dc3o = x[10 * NF];
-        const T dn1n = x[11 * NF], dc1n = x[12 * NF], dc3n = x[13 * NF];
-        const T t11 = T(c[K_XT11]), t13 = T(c[K_XT13]), t21 = T(c[K_XT21]), t22 = T(c[K_XT22]);
-        const T d11o = c1o + t11, d13o = c3o + t13, d21o = c1o + t21, d22o = n1o + t22;
-        const T d11n = c1n + t11, d13n = c3n + t13, d21n = c1n + t21, d22n = n1n + t22;
-        if (e0 + l < E && !(d11o > T(0) && d13o > T(0) && d21o > T(0) && d22o > T(0) &&
-                            d11n > T(0) && d13n > T(0) && d21n > T(0) && d22n > T(0)))
-          flag |= FLAG_DOMAIN;
-        T r11o, r13o, r21o, r22o, r11n, r13n, r21n, r22n;
-        recip4(d11o, d13o, d21o, d22o, r11o, r13o, r21o, r22o);
-        recip4(d11n, d13n, d21n, d22n, r11n, r13n, r21n, r22n);
-        const T w1o = so * (T(c[K_X011]) * dc1o * r11o + T(c[K_X013]) * dc3o * r13o);
-        const T w2o = so * (T(c[K_X021]) * dc1o * r21o - T(c[K_X022]) * dn1o * r22o);
-        const T w1n = so * (T(c[K_X011]) * dc1n * r11n + T(c[K_X013]) * dc3n * r13n);
-        const T w2n = so * (T(c[K_X021]) * dc1n * r21n - T(c[K_X022]) * dn1n * r22n);
-        const T lam = fmax(fmax(fabs(w1o), fabs(w2o)), fmax(fabs(w1n), fabs(w2n)));
-        x[0] = T(0.5) * lam;
-        x[NF] = -T(0.5) * (n1o * w1o + n1n * w1n);
-        x[2 * NF] = -T(0.5) * (n2o * w2o + n2n * w2n);
-      } else {
-        T q1 = T(0), q2 = T(0), q5 = T(0);
-        if (nbl == -1) {
-          if (c1o - T(c[K_C1S]) > T(0)) q1 = T(c[K_MU1] * c[K_BE1]);
-          const int tb0 = t % Q;
-          const double xc = (cell_coord<D>(g, cell_of<D>(g, e0 + l), b0) + tb.x[tb0]) * g.h[b0];
-          if (xc >= g.g1in[0] && xc <= g.g1in[1]) q5 = T(c[K_NU2] * c[K_SIG]);
-        } else if (nbl == -2) {
-          if (c1o - T(c[K_C1SS]) > T(0)) q2 = T(c[K_MU2] * c[K_BE2]);
-        }
-        x[0] = T(0);
-        x[NF] = T(0);
-        x[2 * NF] = T(0);
-        x[3 * NF] = q1;
-        x[4 * NF] = q2;
-        x[5 * NF] = q5;
-      }
-    }
+    face_points<D, Q, NF, EB, FST, true, T>(Fx, sm.nb, f, sg, b0, c, g, tb, e0, E, tid, flag);
     __syncthreads();
     // species pass: nonlinear flux at the points, projected on the tangential modes,
     // plus the linear face terms; spread onto the normal modes

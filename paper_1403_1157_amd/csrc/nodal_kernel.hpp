@@ -542,53 +542,10 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
       park[NF + t] = wo * duo[t] + wn * dun[t];
     }
     nd_sync();
-    // face point pass
+    // face point pass (kind 4 keeps one point per thread: with the split points its
+    // register allocation spilled 17 VGPRs)
     const int b0 = a == 0 ? 1 : 0;   // first tangential axis
-    for (int it = tid; it < EB * NF; it += NT) {
-      const int l = it / NF, t = it % NF;
-      T* x = Fx + l * FST + t;
-      const int nbl = sm.nb[l][f];
-      const T c1o = x[2 * NF];
-      if (nbl >= 0) {
-        const T so = sg ? T(1) : T(-1);
-        const T n1o = x[0], n2o = x[NF], c3o = x[3 * NF];
-        const T n1n = x[4 * NF], n2n = x[5 * NF], c1n = x[6 * NF], c3n = x[7 * NF];
-        const T dn1o = x[8 * NF], dc1o = x[9 * NF], dc3o = x[10 * NF];
-        const T dn1n = x[11 * NF], dc1n = x[12 * NF], dc3n = x[13 * NF];
-        const T t11 = T(c[K_XT11]), t13 = T(c[K_XT13]), t21 = T(c[K_XT21]), t22 = T(c[K_XT22]);
-        const T d11o = c1o + t11, d13o = c3o + t13, d21o = c1o + t21, d22o = n1o + t22;
-        const T d11n = c1n + t11, d13n = c3n + t13, d21n = c1n + t21, d22n = n1n + t22;
-        if (e0 + l < E && !(d11o > T(0) && d13o > T(0) && d21o > T(0) && d22o > T(0) &&
-                            d11n > T(0) && d13n > T(0) && d21n > T(0) && d22n > T(0)))
-          flag |= FLAG_DOMAIN;
-        T r11o, r13o, r21o, r22o, r11n, r13n, r21n, r22n;
-        recip4(d11o, d13o, d21o, d22o, r11o, r13o, r21o, r22o);
-        recip4(d11n, d13n, d21n, d22n, r11n, r13n, r21n, r22n);
-        const T w1o = so * (T(c[K_X011]) * dc1o * r11o + T(c[K_X013]) * dc3o * r13o);
-        const T w2o = so * (T(c[K_X021]) * dc1o * r21o - T(c[K_X022]) * dn1o * r22o);
-        const T w1n = so * (T(c[K_X011]) * dc1n * r11n + T(c[K_X013]) * dc3n * r13n);
-        const T w2n = so * (T(c[K_X021]) * dc1n * r21n - T(c[K_X022]) * dn1n * r22n);
-        const T lam = fmax(fmax(fabs(w1o), fabs(w2o)), fmax(fabs(w1n), fabs(w2n)));
-        x[0] = T(0.5) * lam;
-        x[NF] = -T(0.5) * (n1o * w1o + n1n * w1n);
-        x[2 * NF] = -T(0.5) * (n2o * w2o + n2n * w2n);
-      } else {
-        T q1 = T(0), q2 = T(0), q5 = T(0);
-        if (nbl == -1) {
-          if (c1o - T(c[K_C1S]) > T(0)) q1 = T(c[K_MU1] * c[K_BE1]);
-          const double xc = (cell_coord<D>(g, cell_of<D>(g, e0 + l), b0) + tb.x[t % Q]) * g.h[b0];
-          if (xc >= g.g1in[0] && xc <= g.g1in[1]) q5 = T(c[K_NU2] * c[K_SIG]);
-        } else if (nbl == -2) {
-          if (c1o - T(c[K_C1SS]) > T(0)) q2 = T(c[K_MU2] * c[K_BE2]);
-        }
-        x[0] = T(0);
-        x[NF] = T(0);
-        x[2 * NF] = T(0);
-        x[3 * NF] = q1;
-        x[4 * NF] = q2;
-        x[5 * NF] = q5;
-      }
-    }
+    face_points<D, Q, NF, EB, FST, KIND != 4, T>(Fx, sm.nb, f, sg, b0, c, g, tb, e0, E, tid, flag);
     nd_sync();
     // species pass: all face terms at the face points, weighted, spread onto the
     // Lagrange functions of the normal line through each point
