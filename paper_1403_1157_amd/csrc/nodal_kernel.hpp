@@ -565,12 +565,14 @@ __device__ __forceinline__ void nd_block(const Params& prm, const T* __restrict_
       const T le0 = T(tb.Le[sg][0]), le1 = T(tb.Le[sg][1]), dle0 = T(tb.dLe[sg][0]), dle1 = T(tb.dLe[sg][1]);
       const T le2 = T(tb.Le[sg][Q - 1]), dle2 = T(tb.dLe[sg][Q - 1]);
       const T* park = sm.buf + nd_park_base<P, T, EB>() + tid * nd_park_stride<P>();
+      // the per-face factors (area, the 0/1 weights) folded once
+      const T fa = li * ar, cs = fa * so * as, cp = fa * pen, cd = fa * dw, ck = kw * ar, ch = fa * hs;
 #pragma unroll
       for (int t = 0; t < NF; ++t) {
         const T jm = park[t], sd = park[NF + t];
-        const T wa = ar * T(ct.w[t % Q] * ct.w[t / Q]);
-        const T gv = li * (so * as * sd - (pen + dw * x[t]) * jm) + kw * x[ksl * NF + t];
-        const T G = wa * gv, H = li * wa * (hs * jm);
+        const T wq = T(ct.w[t % Q] * ct.w[t / Q]);
+        const T G = wq * (cs * sd - (cp + cd * x[t]) * jm + ck * x[ksl * NF + t]);
+        const T H = (wq * ch) * jm;
         // spread at once onto the normal line through the point
         R[face_mode<D, Q>(a, 0, t)] += le0 * G + dle0 * H;
         if (Q == 3) R[face_mode<D, Q>(a, 1, t)] += le1 * G + dle1 * H;
