@@ -244,9 +244,10 @@ hipError_t dispatch_cfl(cdg2_handle* h, const void* U) {
   return hipErrorInvalidValue;
 }
 
-// Cells per adjoint workgroup: 21 cells = 126 threads = two wavefronts, so that
-// at two waves per SIMD (the register budget of the adjoint) four workgroups
-// fill all eight wave slots of a CU.
+// Cells per adjoint workgroup: 21 cells = 126 threads = two wavefronts.  The
+// adjoint's registers allow two waves per SIMD (2D p <= 2, 3D p = 1) or one:
+// two-wave workgroups fill all eight (or four) wave slots of a CU, where
+// three-wave ones left two (or one) idle.
 constexpr int ADJ_EB = 21;
 
 template <int D, int P>
