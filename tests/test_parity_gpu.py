@@ -45,6 +45,10 @@ APPLY_CASES = [
     (3, (4, 3, 5), 3, "strong", None, "cells", (0, 1)),
     (3, (3, 4, 2), 2, "strong", 1, "all", (0, 1)),
     (3, (4, 3, 11), 2, "strong", None, "all", (0, 1)),      # two z-slabs of the processing order, ragged
+    # the face point passes split their leftover points into own and neighbour
+    # halves (2D p <= 2, 3D p = 2): inflow walls and ragged workgroups among them
+    (2, (9, 7), 1, "strong", 0, "all", (0.2, 0.7)),
+    (3, (7, 5, 3), 2, "strong", 0, "all", (0.1, 0.6)),
 ]
 
 
